@@ -1,0 +1,390 @@
+"""Python driver of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It composes the plain C functions of lbks_oracle.c into
+one relaxation step in the order the method defines it, and evaluates the
+energies.  It never touches the GPU library.
+
+One step (lattice Boltzmann equation per orbital with the orthogonalisation
+source, section "The kinetic approach to Kohn-Sham theory"):
+  1. psi_j = sum_p f_jp                                   (kinetic representation)
+  2. S_jk = <psi_j|psi_k>                                  (orthogonality constraints)
+  3. orthonormalise: GS  psi_hat = psi C, g = f C, C = L^{-T}, S = L L^T,
+                     W   psi_hat = psi / n, psi* = psi_hat - sum_{l<j} Lambda_jl psi_hat_l
+  4. rho = sum_j occ_j psi_hat_j^2                         (density)
+  5. Hartree: multipole ghost values, K_P red/black SOR sweeps
+  6. V = V_ext + V_H + v_xc(rho)                           (KS potential)
+  7. collide: f^post = (1-omega) g + omega xi psi* - dt chi V psi_hat
+  8. stream with zero inflow from outside the box.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbks_oracle.so")
+SRC_PATH = os.path.join(_HERE, "lbks_oracle.c")
+
+XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81 = 0, 1, 2, 3
+Q = 19
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, OpenMP, no host-specific ISA)."""
+    import subprocess
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_longlong
+        I = ctypes.c_int
+        D = ctypes.c_double
+        sig = {
+            "orc_lattice": (I, [D, P, P, P, P, P]),
+            "orc_dot": (D, [i64, P, P]),
+            "orc_sum": (D, [i64, P]),
+            "orc_moment": (None, [I, i64, P, P]),
+            "orc_overlap": (None, [I, i64, D, P, P]),
+            "orc_cholesky_inverse": (I, [I, P, P]),
+            "orc_combine": (None, [I, i64, P, P, P]),
+            "orc_w_fields": (None, [I, i64, P, P, P, P, P, P]),
+            "orc_density": (None, [I, i64, P, P, P]),
+            "orc_multipoles": (None, [I, I, I, D, P, P]),
+            "orc_multipole_value": (D, [P, D, D, D]),
+            "orc_boundary": (None, [I, I, I, D, P, P]),
+            "orc_sor_omega": (D, [I, I, I]),
+            "orc_sor_sweep": (None, [I, I, I, D, D, P, P]),
+            "orc_poisson_residual": (D, [I, I, I, D, P, P]),
+            "orc_vh_interior": (None, [I, I, I, P, P]),
+            "orc_vext": (None, [I, I, I, D, I, P, P, D, P]),
+            "orc_enn": (D, [I, P, P]),
+            "orc_xc": (None, [I, i64, P, D, P, P, P, P]),
+            "orc_collide": (None, [I, i64, D, D, P, P, P, P, P, P, P]),
+            "orc_stream": (None, [I, I, I, I, P, P, P]),
+            "orc_equilibrium": (None, [I, i64, P, P, P]),
+            "orc_apply_sw": (None, [I, I, I, P, P, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+# ------------------------------------------------------------------ lattice
+
+def lattice(D: float = 1.0 / 3.0):
+    """(v[19,3] int (x,y,z), w, xi, chi) of the D3Q19 reading."""
+    v = np.zeros((Q, 3), dtype=np.int32)
+    w = np.zeros(Q)
+    xi = np.zeros(Q)
+    chi = np.zeros(Q)
+    n = lib().orc_lattice(D, _p(v), _p(w), _p(xi), _p(chi), None)
+    assert n == Q
+    return v, w, xi, chi
+
+
+def occupations(n_elec: int, n_orb: int) -> np.ndarray:
+    """Closed-shell reading: 2 electrons per orbital, the last takes the rest."""
+    occ = np.full(n_orb, 2.0)
+    occ[-1] = n_elec - 2.0 * (n_orb - 1)
+    return occ
+
+
+def time_step(omega: float, D: float, h: float) -> float:
+    """Physical imaginary-time step of one lattice step: the lattice diffusivity
+    (1/omega - 1/2) D must equal hbar/2m = 1/2 in atomic units, so
+    Delta t = 2 (1/omega - 1/2) D h^2."""
+    return 2.0 * (1.0 / omega - 0.5) * D * h * h
+
+
+def xc_fields(kind: int, rho: np.ndarray, floor: float = 1e-14):
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    n = rho.size
+    ex, ec, vx, vc = (np.zeros_like(rho) for _ in range(4))
+    lib().orc_xc(kind, n, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
+    return ex, ec, vx, vc
+
+
+def apply_sw(dims, v, wts, u):
+    nx, ny, nz = dims
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.empty_like(u)
+    lib().orc_apply_sw(nx, ny, nz, _p(np.ascontiguousarray(v, dtype=np.int32)),
+                       _p(np.ascontiguousarray(wts, dtype=np.float64)), _p(u), _p(out))
+    return out
+
+
+# --------------------------------------------------------------------- solver
+
+@dataclass
+class Params:
+    dims: tuple
+    h: float
+    n_orb: int
+    n_elec: int
+    omega: float = 1.0
+    D: float = 1.0 / 3.0
+    ortho: str = "gs"             # "gs" or "w"
+    xc: int = XC_X_LYPLOCAL
+    hartree: bool = True
+    poisson_sweeps: int = 2
+    softening: float = 0.05
+    rho_floor: float = 1e-14
+    occ: Optional[np.ndarray] = None
+
+    @property
+    def dt(self) -> float:
+        return time_step(self.omega, self.D, self.h)
+
+    @property
+    def n_sites(self) -> int:
+        return self.dims[0] * self.dims[1] * self.dims[2]
+
+
+@dataclass
+class Energies:
+    e_total: float
+    e_kin: float
+    e_ext: float
+    e_hartree: float
+    e_x: float
+    e_c: float
+    e_nn: float
+    n_electrons: float
+    poisson_residual: float
+    eps: np.ndarray
+    steps: int
+    extra: dict = field(default_factory=dict)
+
+
+class Oracle:
+    """State (f, V_H) of one solve, advanced one plain step at a time."""
+
+    def __init__(self, prm: Params):
+        self.prm = prm
+        self.L = lib()
+        nx, ny, nz = prm.dims
+        self.N = prm.n_sites
+        self.v, self.w, self.xi, self.chi = lattice(prm.D)
+        self.occ = (np.asarray(prm.occ, dtype=np.float64) if prm.occ is not None
+                    else occupations(prm.n_elec, prm.n_orb))
+        self.f = np.zeros((prm.n_orb, Q, self.N))
+        self.fpost = np.zeros_like(self.f)
+        self.vh = np.zeros((nz + 2, ny + 2, nx + 2))
+        self.vext = None
+        self.e_nn = 0.0
+        self.steps = 0
+        self.omega_sor = self.L.orc_sor_omega(nx, ny, nz)
+
+    # -- inputs
+    def set_nuclei(self, Z, R):
+        nx, ny, nz = self.prm.dims
+        Z = np.ascontiguousarray(Z, dtype=np.float64)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1, 3)
+        self.vext = np.zeros(self.N)
+        self.L.orc_vext(nx, ny, nz, self.prm.h, len(Z), _p(Z), _p(R), self.prm.softening,
+                        _p(self.vext))
+        self.e_nn = self.L.orc_enn(len(Z), _p(Z), _p(R))
+
+    def set_potential(self, vext):
+        self.vext = np.ascontiguousarray(vext, dtype=np.float64).reshape(self.N).copy()
+        self.e_nn = 0.0
+
+    def set_orbitals(self, psi0):
+        psi0 = np.ascontiguousarray(psi0, dtype=np.float64).reshape(self.prm.n_orb, self.N)
+        self.L.orc_equilibrium(self.prm.n_orb, self.N, _p(self.xi), _p(psi0), _p(self.f))
+
+    # -- pieces of one step
+    def moment(self):
+        psi = np.empty((self.prm.n_orb, self.N))
+        self.L.orc_moment(self.prm.n_orb, self.N, _p(self.f), _p(psi))
+        return psi
+
+    def overlap(self, psi):
+        S = np.empty((self.prm.n_orb, self.prm.n_orb))
+        self.L.orc_overlap(self.prm.n_orb, self.N, self.prm.h, _p(psi), _p(S))
+        return S
+
+    def orthonormalise(self, psi, with_g=True):
+        """Returns (psi_hat, psi_star, g, S)."""
+        n = self.prm.n_orb
+        S = self.overlap(psi)
+        if self.prm.ortho == "gs":
+            C = np.empty((n, n))
+            rc = self.L.orc_cholesky_inverse(n, _p(S), _p(C))
+            if rc != 0:
+                raise FloatingPointError("overlap matrix is not positive definite")
+            psihat = np.empty_like(psi)
+            self.L.orc_combine(n, self.N, _p(C), _p(psi), _p(psihat))
+            g = None
+            if with_g:
+                g = np.empty_like(self.f)
+                self.L.orc_combine(n, Q * self.N, _p(C), _p(self.f), _p(g))
+            return psihat, psihat, g, S
+        psihat = np.empty_like(psi)
+        psistar = np.empty_like(psi)
+        g = np.empty_like(self.f)
+        self.L.orc_w_fields(n, self.N, _p(S), _p(psi), _p(self.f), _p(psihat), _p(psistar), _p(g))
+        return psihat, psistar, g, S
+
+    def density(self, psihat):
+        rho = np.empty(self.N)
+        self.L.orc_density(self.prm.n_orb, self.N, _p(self.occ), _p(psihat), _p(rho))
+        return rho
+
+    def hartree_boundary(self, rho):
+        nx, ny, nz = self.prm.dims
+        m = np.empty(10)
+        self.L.orc_multipoles(nx, ny, nz, self.prm.h, _p(rho), _p(m))
+        self.L.orc_boundary(nx, ny, nz, self.prm.h, _p(m), _p(self.vh))
+        return m
+
+    def sor(self, rho, sweeps):
+        nx, ny, nz = self.prm.dims
+        for _ in range(sweeps):
+            self.L.orc_sor_sweep(nx, ny, nz, self.prm.h, self.omega_sor, _p(rho), _p(self.vh))
+
+    def poisson_residual(self, rho):
+        nx, ny, nz = self.prm.dims
+        return self.L.orc_poisson_residual(nx, ny, nz, self.prm.h, _p(rho), _p(self.vh))
+
+    def vh_interior(self):
+        nx, ny, nz = self.prm.dims
+        out = np.empty(self.N)
+        self.L.orc_vh_interior(nx, ny, nz, _p(self.vh), _p(out))
+        return out
+
+    def potential(self, rho):
+        """V = V_ext + V_H + v_x + v_c, plus the xc fields used for energies."""
+        V = self.vext.copy()
+        if self.prm.hartree:
+            V += self.vh_interior()
+        ex, ec, vx, vc = xc_fields(self.prm.xc, rho, self.prm.rho_floor)
+        if self.prm.xc != XC_NONE:
+            V += vx
+            V += vc
+        return V, (ex, ec, vx, vc)
+
+    def step(self):
+        if self.vext is None:
+            raise RuntimeError("no potential set")
+        p = self.prm
+        psi = self.moment()
+        psihat, psistar, g, _ = self.orthonormalise(psi)
+        rho = self.density(psihat)
+        if p.hartree:
+            self.hartree_boundary(rho)
+            self.sor(rho, p.poisson_sweeps)
+        V, _ = self.potential(rho)
+        self.L.orc_collide(p.n_orb, self.N, p.omega, p.dt, _p(self.xi), _p(self.chi), _p(g),
+                           _p(psistar), _p(psihat), _p(V), _p(self.fpost))
+        nx, ny, nz = p.dims
+        self.L.orc_stream(p.n_orb, nx, ny, nz, _p(self.v), _p(self.fpost), _p(self.f))
+        self.steps += 1
+
+    # -- results
+    def state(self):
+        """(psi_hat, rho) of the current populations."""
+        psihat, _, _, _ = self.orthonormalise(self.moment(), with_g=False)
+        return psihat, self.density(psihat)
+
+    def converge_poisson(self, rho, tol=1e-12, block=10, max_sweeps=200000):
+        self.hartree_boundary(rho)
+        sweeps = 0
+        res = self.poisson_residual(rho)
+        while res > tol and sweeps < max_sweeps:
+            self.sor(rho, block)
+            sweeps += block
+            res = self.poisson_residual(rho)
+        return res, sweeps
+
+    def energies(self, converge_poisson=True, tol=1e-12) -> Energies:
+        p = self.prm
+        h3 = p.h ** 3
+        psihat, _, _, _ = self.orthonormalise(self.moment(), with_g=False)
+        rho = self.density(psihat)
+        res = 0.0
+        if p.hartree:
+            if converge_poisson:
+                res, _ = self.converge_poisson(rho, tol)
+            else:
+                res = self.poisson_residual(rho)
+        V, (ex, ec, vx, vc) = self.potential(rho)
+        dims = p.dims
+        eps = np.empty(p.n_orb)
+        e_kin = 0.0
+        D = self.L.orc_dot
+        for j in range(p.n_orb):
+            u = np.ascontiguousarray(psihat[j])
+            su = apply_sw(dims, self.v, self.xi, u)
+            ku = -(su - u) / (p.D * p.h * p.h)          # K_h u
+            vu = apply_sw(dims, self.v, self.chi, V * u)  # S_chi (V u)
+            kin = h3 * D(self.N, _p(u), _p(np.ascontiguousarray(ku)))
+            pot = h3 * D(self.N, _p(u), _p(vu))
+            eps[j] = kin + pot
+            e_kin += self.occ[j] * kin
+        e_ext = h3 * D(self.N, _p(self.vext), _p(rho))
+        e_h = 0.5 * h3 * D(self.N, _p(np.ascontiguousarray(self.vh_interior())), _p(rho)) if p.hartree else 0.0
+        e_x = h3 * D(self.N, _p(rho), _p(ex)) if p.xc != XC_NONE else 0.0
+        e_c = h3 * D(self.N, _p(rho), _p(ec)) if p.xc != XC_NONE else 0.0
+        ne = h3 * self.L.orc_sum(self.N, _p(rho))
+        et = e_kin + e_ext + e_h + e_x + e_c + self.e_nn
+        return Energies(et, e_kin, e_ext, e_h, e_x, e_c, self.e_nn, ne, res, eps, self.steps)
+
+    def relax(self, max_steps, dE_tol=0.0, check_every=100):
+        """Run steps in chunks of check_every; after each chunk (only if dE_tol > 0)
+        the total energy with the current Hartree potential is compared with the
+        previous chunk's.  Returns (0 converged | 1 step limit, steps done)."""
+        done = 0
+        e_prev = None
+        check_every = max(1, int(check_every))
+        while done < max_steps:
+            n = min(check_every, max_steps - done)
+            for _ in range(n):
+                self.step()
+            done += n
+            if dE_tol > 0:
+                e = self.energies(converge_poisson=False).e_total
+                if e_prev is not None and abs(e - e_prev) < dE_tol:
+                    return 0, done
+                e_prev = e
+        return 1, done
+
+
+def params_for(system, **kw) -> Params:
+    """Oracle parameters for an inputs.System."""
+    return Params(dims=tuple(system.dims), h=system.h, n_orb=system.n_orb, n_elec=system.n_elec,
+                  softening=system.softening, **kw)
+
+
+def oracle_for(system, **kw) -> Oracle:
+    o = Oracle(params_for(system, **kw))
+    o.set_nuclei(system.Z, system.R)
+    o.set_orbitals(system.psi0())
+    return o

@@ -1,0 +1,188 @@
+"""Physical pins of the oracle: continuum limits and self-consistency.
+
+  * diffusion: with V = 0 the lattice diffusivity is (1/omega - 1/2) D and one
+    step is dt = 2 (1/omega - 1/2) D h^2 of imaginary time, so the imaginary-time
+    Schroedinger equation's diffusion constant hbar/2m = 1/2 is recovered;
+  * kinetic energy of a Gaussian, 3 / (4 sigma^2), to O(h^2);
+  * harmonic oscillator (Hartree and xc off): (n + 3/2) w0 with degeneracies 1, 3
+    after Richardson extrapolation in h;
+  * softened Coulomb well: the 3-D ground level extrapolates to the exact eigenvalue
+    of the radial equation solved on a fine 1-D grid;
+  * the self-consistent He-like fixed point at 12^3 is the dominant eigenvector of
+    M[V] with V rebuilt from the converged density;
+  * electron count and the relaxation's stopping rule.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import eigh_tridiagonal
+
+from paper_1507_07666_amd.inputs import node_coords, radius2
+from test_oracle_spectral import relaxation_matrix, subspace_distance
+from test_oracle_poisson_xc import dst_poisson
+
+
+def fixed(O, dims, h, n_orb, V, seed=0, omega=1.0):
+    prm = O.Params(dims, h, n_orb, 2 * n_orb, omega=omega, xc=O.XC_NONE, hartree=False)
+    o = O.Oracle(prm)
+    o.set_potential(V)
+    rng = np.random.default_rng(seed)
+    o.set_orbitals(rng.standard_normal((n_orb, prm.n_sites)))
+    return o
+
+
+@pytest.mark.parametrize("omega", [1.0, 0.8])
+def test_gaussian_spreads_with_physical_diffusivity(oracle_mod, omega):
+    O = oracle_mod
+    n, h = 64, 0.25
+    dims = (n, n, n)
+    prm = O.Params(dims, h, 1, 2, omega=omega, xc=O.XC_NONE, hartree=False)
+    o = O.Oracle(prm)
+    o.set_potential(np.zeros(prm.n_sites))
+    x = node_coords(n, h)
+    s0 = 3.0 * h
+    o.set_orbitals(np.exp(-radius2(dims, h) / (2 * s0 * s0)).ravel()[None])
+
+    def var_x():
+        psi, _ = o.state()
+        g = psi[0].reshape(n, n, n)
+        px = g.sum((0, 1))
+        m1 = (px * x).sum() / px.sum()
+        return (px * x * x).sum() / px.sum() - m1 * m1
+
+    for _ in range(10):
+        o.step()
+    v10 = var_x()
+    for _ in range(30):
+        o.step()
+    v40 = var_x()
+    rate = (v40 - v10) / 30.0              # bohr^2 per step = 2 * (physical D) * dt
+    assert abs(rate / (2.0 * prm.dt) - 0.5) < 1e-6
+
+
+def test_gaussian_kinetic_energy_second_order(oracle_mod):
+    O = oracle_mod
+    errs = []
+    for h in (0.2, 0.1):
+        n = int(round(11.2 / h)) + 1
+        dims = (n, n, n)
+        prm = O.Params(dims, h, 1, 2, xc=O.XC_NONE, hartree=False)
+        o = O.Oracle(prm)
+        o.set_potential(np.zeros(prm.n_sites))
+        o.set_orbitals(np.exp(-radius2(dims, h) / 2.0).ravel()[None])
+        e = o.energies(converge_poisson=False)
+        errs.append(e.eps[0] - 0.75)
+    assert abs(errs[0]) < 1e-2
+    assert abs(errs[0] / errs[1] - 4.0) < 0.1
+
+
+def test_harmonic_oscillator_spectrum(oracle_mod):
+    O = oracle_mod
+    w0, L = 2.0, 2.4
+    res = {}
+    for h in (0.2, 0.15):
+        n = int(round(2 * L / h)) + 1
+        dims = (n, n, n)
+        V = 0.5 * w0 * w0 * radius2(dims, h).ravel()
+        o = fixed(O, dims, h, 4, V)
+        steps = int(math.log(1e-12) / (-2.0 * w0 * h * h / 3.0))
+        for _ in range(steps):
+            o.step()
+        res[h] = o.energies(converge_poisson=False).eps
+    e2, e1 = res[0.2], res[0.15]
+    rich = (e1 * 0.2 ** 2 - e2 * 0.15 ** 2) / (0.2 ** 2 - 0.15 ** 2)
+    assert abs(rich[0] - 1.5 * w0) < 1e-3
+    assert np.allclose(rich[1:], 2.5 * w0, atol=3e-3)
+    assert np.ptp(e1[1:]) < 1e-9                      # threefold degenerate p level
+    assert abs((3.0 - e2[0]) / (3.0 - e1[0]) - (0.2 / 0.15) ** 2) < 0.05
+
+
+def radial_ground_level(Z, a, R=14.0, n=100000):
+    """Lowest s level of -1/2 u'' - Z u / sqrt(r^2 + a^2) = E u, u(0) = u(R) = 0."""
+    r = np.linspace(0.0, R, n + 2)[1:-1]
+    dr = r[1] - r[0]
+    d = 1.0 / dr ** 2 - Z / np.sqrt(r * r + a * a)
+    e = np.full(n - 1, -0.5 / dr ** 2)
+    return float(eigh_tridiagonal(d, e, select="i", select_range=(0, 0), eigvals_only=True)[0])
+
+
+def test_softened_coulomb_ground_level(oracle_mod):
+    O = oracle_mod
+    Z, a, L = 4.0, 0.5, 4.0
+    exact = radial_ground_level(Z, a)
+    res = {}
+    for h in (0.2, 0.15):
+        n = int(round(2 * L / h)) + 1
+        dims = (n, n, n)
+        V = -Z / np.sqrt(radius2(dims, h).ravel() + a * a)
+        o = fixed(O, dims, h, 1, V)
+        for _ in range(int(math.log(1e-12) / (-3.0 * h * h / 3.0))):
+            o.step()
+        res[h] = o.energies(converge_poisson=False).eps[0]
+    rich = (res[0.15] * 0.2 ** 2 - res[0.2] * 0.15 ** 2) / (0.2 ** 2 - 0.15 ** 2)
+    assert abs(rich - exact) < 5e-4
+    assert res[0.2] < res[0.15] < exact + 1e-12 or res[0.2] > res[0.15] > exact - 1e-12
+
+
+def test_scf_fixed_point_is_dominant_eigenvector(oracle_mod):
+    """He-like SCF on 12^3: after convergence, psi_hat is the dominant eigenvector of
+    M = S_xi - dt S_chi diag(V) with V = V_ext + V_H + v_xc rebuilt from rho; V_H is the
+    exact discrete Poisson solution for that rho."""
+    O = oracle_mod
+    dims, h, Z, a = (12, 12, 12), 0.4, 2.0, 0.3
+    prm = O.Params(dims, h, 1, 2, softening=a, xc=O.XC_X_LYPLOCAL, hartree=True)
+    o = O.Oracle(prm)
+    o.set_nuclei([Z], [[0.0, 0.0, 0.0]])
+    o.set_orbitals(np.exp(-radius2(dims, h) / 2.0).ravel()[None])
+    rc, _ = o.relax(6000, dE_tol=1e-14, check_every=50)
+    assert rc == 0
+    e = o.energies(converge_poisson=True, tol=1e-13)
+    psihat, rho = o.state()
+    assert abs(h ** 3 * rho.sum() - 2.0) < 1e-12
+    vext = -Z / np.sqrt(radius2(dims, h).ravel() + a * a)
+    vh = dst_poisson(rho, o.vh, dims, h)
+    assert np.max(np.abs(vh - o.vh_interior())) < 1e-10
+    _, _, vx, vc = O.xc_fields(O.XC_X_LYPLOCAL, rho)
+    V = vext + vh + vx + vc
+    M, dt = relaxation_matrix(dims, h, V, O)
+    w, vr = np.linalg.eig(M)
+    top = vr[:, np.argmax(w.real)].real
+    assert subspace_distance(psihat.T, top[:, None]) < 1e-8
+    assert abs(e.eps[0] - (1.0 - w.real.max()) / dt) < 1e-8
+
+
+def test_electron_count_of_orthonormalised_orbitals(oracle_mod):
+    O = oracle_mod
+    from paper_1507_07666_amd import inputs as I
+    s = I.ne_atom().scaled(16)
+    o = O.oracle_for(s)
+    psihat, rho = o.state()
+    G = s.h ** 3 * psihat @ psihat.T
+    assert np.allclose(G, np.eye(5), atol=1e-12)
+    assert abs(s.h ** 3 * rho.sum() - 10.0) < 1e-12
+    for _ in range(3):
+        o.step()
+    assert abs(o.energies(converge_poisson=False).n_electrons - 10.0) < 1e-12
+
+
+def test_relax_stopping_rule(oracle_mod):
+    O = oracle_mod
+    from paper_1507_07666_amd import inputs as I
+    s = I.he_atom().scaled(12, h=0.4)
+    o = O.oracle_for(s)
+    rc, steps = o.relax(37, dE_tol=0.0, check_every=10)
+    assert (rc, steps, o.steps) == (1, 37, 37)
+    rc, steps = o.relax(5000, dE_tol=1e-9, check_every=25)
+    assert rc == 0 and steps % 25 == 0 and steps < 5000
+    rc2, steps2 = o.relax(5000, dE_tol=1e-9, check_every=25)
+    assert rc2 == 0 and steps2 == 50      # already converged: two checks
+
+
+def test_nuclear_repulsion_closed_form(oracle_mod):
+    O = oracle_mod
+    prm = O.Params((4, 4, 4), 0.5, 1, 2)
+    o = O.Oracle(prm)
+    o.set_nuclei([3.0, 2.0, 1.0], [[0, 0, 0], [1.7, 0, 0], [0, 0, 2.5]])
+    d23 = math.hypot(1.7, 2.5)
+    assert abs(o.e_nn - (6.0 / 1.7 + 3.0 / 2.5 + 2.0 / d23)) < 1e-14
