@@ -1,0 +1,141 @@
+"""Throughput of the lattice kinetic Kohn-Sham relaxation on one MI355X.
+
+A step is one lattice step of the whole hot path for every orbital: overlap +
+Cholesky Gram-Schmidt, density, Hartree SOR sweeps, potential with local xc,
+and the population stream-collide; the energy evaluation and convergence test
+run every `--check-every` steps inside the timed region.
+
+Default workload: Ne atom, 96^3 nodes at 0.2 bohr, softening 0.05, 5 orbitals,
+FP64, seeded random Gaussian-enveloped start (seed 2).  Metric: orbital-site
+updates per second (orbitals x nodes x steps / wall time), inputs resident in
+HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    from paper_1507_07666_amd import inputs as I
+    if name == "ne96":
+        return I.ne_atom()
+    if name == "he32":
+        return I.he_atom()
+    if name == "ch4":
+        return I.ch4()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def k1_bytes_per_launch(n_orb, nsite, s, scheme):
+    """Algorithmic HBM bytes of one stream-collide launch: per orbital-site 2 Q s
+    (populations in and out) + s (psi_hat stencil centre, read once) + s (psi out);
+    per site s (potential).  The collapsed scheme moves only 2 s per orbital-site + s."""
+    if scheme == 0:
+        return nsite * (n_orb * (2 * 19 * s + 2 * s) + s)
+    return nsite * (n_orb * 2 * s + s)
+
+
+def cpu_baseline(system, steps, threads):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    o = O.oracle_for(system)
+    o.step()                      # warm caches / first-touch
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.step()
+    dt = time.perf_counter() - t0
+    return {"value": system.n_orb * system.n_sites * steps / dt, "unit": "orbital-site updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} oracle steps of the same workload ({system.name} "
+                      f"{system.dims[0]}^3, {system.n_orb} orbitals, FP64) after 1 untimed step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="ne96")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--scheme", default="populations", choices=["populations", "collapsed"])
+    ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(a solve shards by z-slabs in principle; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1507_07666_amd import lbks
+
+    torch.cuda.set_device(0)
+    system = workload(args.workload)
+    prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
+    scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED
+    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme)
+    s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
+
+    if args.warmup:
+        solver.relax(args.warmup)
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        solver.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, steps = solver.relax(args.steps, dE_tol=1e-30, check_every=args.check_every)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k1_ms, k1_n = solver.kernel_time() if not args.no_timing else (0.0, 0)
+    e = solver.energy()
+    solver.close()
+
+    value = system.n_orb * system.n_sites * steps / elapsed
+    out = {
+        "metric": "orbital-site updates/s",
+        "value": value,
+        "unit": "orbital-site updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / max(1, steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == lbks.LBKS_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{system.name} atom {system.dims[0]}^3 nodes, h={system.h} bohr, "
+                               f"softening {system.softening}, {system.n_orb} orbitals, "
+                               f"{args.precision} {args.scheme}, seed {system.seed}",
+                   "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
+                   "parallelism": "single GPU"},
+        "e_total": e["e_total"],
+    }
+    if k1_n:
+        avg_s = k1_ms / k1_n * 1e-3
+        alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme)
+        ach = alg / avg_s / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed",
+                           "avg_us": avg_s * 1e6, "launches": k1_n, "alg_bytes_per_launch": alg}
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(system, args.cpu_steps, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,250 @@
+/*
+ * lbks.h -- C ABI of the lattice kinetic Kohn-Sham relaxation library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library finds the lowest n_orb Kohn-Sham orbitals, the density, the
+ * total energy and the orbital energies of a set of nuclei (Kohn-Sham
+ * equations with the orthogonality constraints, section "Kohn-Sham
+ * formulation") as the steady state of one lattice Boltzmann imaginary-time
+ * relaxation per orbital, coupled through the self-consistent potential and
+ * the orthogonalisation source (section "The kinetic approach to Kohn-Sham
+ * theory", lattice Boltzmann equation per orbital and its Gram-Schmidt form).
+ *
+ * Units are atomic units (hartree, bohr).  Grids are cubic-celled boxes of
+ * N[0] x N[1] x N[2] nodes with spacing h; node (i, j, k) sits at
+ * ((i - (N[0]-1)/2) h, (j - (N[1]-1)/2) h, (k - (N[2]-1)/2) h), so the origin
+ * is the box centre.  Scalar fields are laid out [k][j][i] (x fastest) and
+ * orbital fields [orbital][k][j][i].
+ *
+ * Conventions for every call:
+ *  - return value 0 (LBKS_OK) on success, a negative LBKS_E_* code on error;
+ *    lbks_last_error() then holds a message.  No C++ exception crosses the ABI.
+ *  - pointer arguments documented as "host" are ordinary CPU memory owned by
+ *    the caller and only read or written during the call.
+ *  - a context is not thread-safe; distinct contexts are independent.
+ *  - all GPU work is enqueued on the stream given at creation; calls that
+ *    return results to the host synchronise that stream.
+ */
+#ifndef LBKS_H
+#define LBKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBKS_MAX_ORB 16
+#define LBKS_MAX_NUC 64
+
+/* status codes */
+#define LBKS_OK 0
+#define LBKS_NOT_CONVERGED 1
+#define LBKS_E_INVAL (-1)
+#define LBKS_E_NOMEM (-2)
+#define LBKS_E_HIP (-3)
+#define LBKS_E_NUMERIC (-4)
+#define LBKS_E_STATE (-5)
+
+/* orthogonalisation: exact Cholesky Gram-Schmidt each step, or the paper's
+ * orthogonalisation source (normalised orbitals, lagged projection
+ * psi*_j = psi_j - sum_{k<j} Lambda_jk psi_k in the equilibrium). */
+#define LBKS_ORTHO_GS 0
+#define LBKS_ORTHO_W 1
+
+/* local exchange-correlation (the paper leaves V_xc open): none, Slater
+ * exchange, Slater + Lee-Yang-Parr correlation at zero density gradient,
+ * Slater + Perdew-Zunger 1981. */
+#define LBKS_XC_NONE 0
+#define LBKS_XC_X 1
+#define LBKS_XC_X_LYPLOCAL 2
+#define LBKS_XC_X_PZ81 3
+
+/* precision: everything in FP64, or populations, orbitals, density and
+ * potential stored and streamed in FP32 while the overlap, Cholesky factor,
+ * Hartree potential, Poisson residual and all energy sums stay FP64. */
+#define LBKS_FP64 0
+#define LBKS_FP32_BULK 1
+
+/* initial orbitals: exp(-r^2/2s^2) + noise (2u-1); exp(-r^2/2s^2)(2u-1);
+ * or supplied later with lbks_set_orbitals.  u is the SplitMix64 draw
+ * k = ((j N[2] + z) N[1] + y) N[0] + x under `seed`, mapped to [0,1) by its
+ * 53 high bits. */
+#define LBKS_INIT_GAUSS_NOISE 0
+#define LBKS_INIT_RANDOM_GAUSS 1
+#define LBKS_INIT_USER 2
+
+/* relaxation scheme: populations f_jp stored and streamed (the lattice
+ * Boltzmann equation as written, any omega), or, at omega = 1 only, the
+ * equivalent update of the orbital fields alone
+ * psi_j <- S_xi psi*_j - dt S_chi (V psi_hat_j), which needs no populations. */
+#define LBKS_SCHEME_POPULATIONS 0
+#define LBKS_SCHEME_COLLAPSED 1
+
+typedef struct lbks_params {
+    int32_t N[3];            /* nodes per axis, each in [4, 1024] */
+    double h;                /* node spacing (bohr) */
+    int32_t n_orb;           /* orbitals, 1..LBKS_MAX_ORB */
+    int32_t n_elec;          /* electrons; occupations 2,2,...,n_elec-2(n_orb-1) */
+    double omega;            /* BGK relaxation frequency (default 1) */
+    double D;                /* second moment of the equilibrium weights xi_p (default 1/3) */
+    int32_t ortho;           /* LBKS_ORTHO_* */
+    int32_t xc;              /* LBKS_XC_* */
+    int32_t hartree;         /* 1: include the Hartree potential */
+    int32_t poisson_sweeps;  /* red/black SOR sweeps per lattice step (default 2) */
+    int32_t precision;       /* LBKS_FP64 or LBKS_FP32_BULK */
+    double softening;        /* a in -Z / sqrt(|r-R|^2 + a^2) (bohr) */
+    int32_t init;            /* LBKS_INIT_* */
+    double init_sigma;       /* s of the initial Gaussian envelope (bohr) */
+    double init_noise;       /* noise amplitude for LBKS_INIT_GAUSS_NOISE */
+    uint64_t seed;           /* SplitMix64 seed of the initial orbitals */
+    double rho_floor;        /* exchange-correlation is zero below this density */
+    int32_t scheme;          /* LBKS_SCHEME_* */
+    int32_t reserved[7];     /* must be zero */
+} lbks_params;
+
+/* Device binding.  `stream` is a hipStream_t (NULL: the library creates one).
+ * `alloc`/`free` (both or neither) route every device allocation of the
+ * context through the caller's allocator, e.g. the PyTorch caching allocator;
+ * NULL means hipMalloc/hipFree.  `device` is the HIP device ordinal. */
+typedef struct lbks_device {
+    void *stream;
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+    int32_t device;
+    int32_t reserved[3];
+} lbks_device;
+
+/* Energies of the current state (hartree).  e_total = e_kin + e_ext +
+ * e_hartree + e_x + e_c + e_nn.  eps[j] = <psi_hat_j|K_h psi_hat_j> +
+ * <psi_hat_j|S_chi (V psi_hat_j)> for j < n_orb (unused entries zero). */
+typedef struct lbks_energies {
+    double e_total, e_kin, e_ext, e_hartree, e_x, e_c, e_nn;
+    double n_electrons;       /* <1|rho> */
+    double poisson_residual;  /* ||lap_h V_H + 4 pi rho|| / ||4 pi rho|| */
+    double eps[LBKS_MAX_ORB];
+    int64_t steps;            /* lattice steps taken since creation */
+} lbks_energies;
+
+typedef struct lbks_ctx lbks_ctx;
+
+/* Fill `p` with the defaults: omega 1, D 1/3, GS, Slater + LYP-local, Hartree
+ * on, 2 SOR sweeps, FP64, softening 0.05, random-Gaussian start of width 1,
+ * seed 0, density floor 1e-14, population scheme.  Grid, h, n_orb and n_elec
+ * are zeroed and must be set. */
+int lbks_params_default(lbks_params *p);
+
+/* Create a solve context and initialise psi^0 and the populations at
+ * equilibrium, f_jp = xi_p psi^0_j (lattice Boltzmann equilibrium).
+ * Rejects (LBKS_E_INVAL) parameters outside the stable region: omega in
+ * (0, 2), D in (0, 7/18] (the relaxation stencil keeps a non-negative symbol),
+ * n_elec in [1, 2 n_orb], a nonzero reserved field, or the collapsed scheme at
+ * omega != 1.  LBKS_E_NOMEM if the device memory cannot be allocated.
+ * The context owns its device memory until lbks_destroy. */
+int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ctx **out);
+
+/* Set the nuclei (host arrays: Z[n], xyz[3n] in bohr relative to the box
+ * centre): rebuilds V_ext(r) = -sum_I Z_I / sqrt(|r - R_I|^2 + a^2) on the
+ * device and the ion-ion energy sum_{I<J} Z_I Z_J / |R_I - R_J| (the nuclear
+ * term of the KS Hamiltonian).  Orbitals and the Hartree potential are kept,
+ * so a geometry scan warm-starts from the previous point.  LBKS_E_INVAL if
+ * n is outside [1, LBKS_MAX_NUC], a charge is not positive, or a nucleus lies
+ * outside the box. */
+int lbks_set_nuclei(lbks_ctx *ctx, int32_t n, const double *Z, const double *xyz);
+
+/* Run lattice steps (lattice Boltzmann equation per orbital with the
+ * orthogonalisation source, then the self-consistent potential).  Steps run
+ * in chunks of `check_every`; if dE_tol > 0 the total energy (with the
+ * current Hartree potential) is evaluated after each chunk and the call
+ * returns LBKS_OK once two consecutive chunk energies differ by less than
+ * dE_tol.  With dE_tol <= 0 exactly max_steps steps run.  Returns
+ * LBKS_NOT_CONVERGED when max_steps is reached, LBKS_E_NUMERIC if the overlap
+ * matrix stops being finite and positive definite, LBKS_E_STATE if no
+ * potential was set.  *steps_done (may be NULL) receives the steps run. */
+int lbks_relax(lbks_ctx *ctx, int64_t max_steps, double dE_tol, int32_t check_every,
+               int64_t *steps_done);
+
+/* Energies of the current state (host struct).  First relaxes the Hartree
+ * potential for the current density to a relative residual <= 1e-12 (this
+ * state change is kept), then evaluates every term of the total energy. */
+int lbks_energy(lbks_ctx *ctx, lbks_energies *out);
+
+/* Copy the current orthonormal orbitals (host, FP64, [n_orb][z][y][x],
+ * n_psi >= n_orb * sites) and optionally the density (host, n_rho >= sites;
+ * rho may be NULL).  <psi_hat_j|psi_hat_k> = delta_jk; each orbital's sign is
+ * arbitrary and degenerate orbitals may mix.  LBKS_E_INVAL if a buffer is too
+ * small. */
+int lbks_orbitals(lbks_ctx *ctx, double *psi, size_t n_psi, double *rho, size_t n_rho);
+
+/* Release the context and all its device memory. */
+void lbks_destroy(lbks_ctx *ctx);
+
+/* Message of the last error on `ctx` (or of the last failed lbks_create when
+ * ctx is NULL).  Valid until the next call on the same context. */
+const char *lbks_last_error(const lbks_ctx *ctx);
+
+/* ---- extensions ---- */
+
+/* Replace V_ext by an arbitrary potential (host, FP64, one value per node);
+ * the ion-ion energy becomes zero.  Used for model wells (harmonic
+ * oscillator, empty box). */
+int lbks_set_potential(lbks_ctx *ctx, const double *v_ext);
+
+/* Replace the orbitals (host, FP64, [n_orb][z][y][x]) and reset the
+ * populations to equilibrium f_jp = xi_p psi_j; the Hartree potential is
+ * kept.  Used for warm starts and checkpoint/resume. */
+int lbks_set_orbitals(lbks_ctx *ctx, const double *psi);
+
+/* Grid nodes and orbital count of a context. */
+int lbks_shape(const lbks_ctx *ctx, int32_t N[3], int32_t *n_orb);
+
+/* Device bytes the context holds. */
+size_t lbks_device_bytes(const lbks_ctx *ctx);
+
+/* Device bytes lbks_create would allocate for these parameters (0 if they are
+ * invalid). */
+size_t lbks_estimate_bytes(const lbks_params *p);
+
+/* Kernel timing: when enabled, every launch of the stream-collide kernel is
+ * bracketed by HIP events on the context's stream.  lbks_kernel_time returns
+ * the summed duration (ms) and the launch count since the last reset, and
+ * synchronises the stream.  kernel: 0 = stream-collide. */
+int lbks_set_timing(lbks_ctx *ctx, int32_t enable);
+int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Plain device-to-device copy of `bytes` on `stream` with the library's own
+ * copy kernel (device pointers, 16-byte aligned); used to calibrate memory
+ * counters against a kernel of known traffic. */
+int lbks_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
+
+/* ---- batches: many solves advanced together, one launch per kernel ---- */
+
+typedef struct lbks_batch lbks_batch;
+
+/* A batch shares one stream and launches each step kernel once for all of its
+ * active contexts (uneven grids and orbital counts), captured into HIP graphs
+ * that are rebuilt when the membership changes.  The contexts stay ordinary
+ * lbks_ctx handles for set_nuclei, energy and orbitals; they must have been
+ * created on the batch's stream and device. */
+int lbks_batch_create(const lbks_device *dev, lbks_batch **out);
+int lbks_batch_attach(lbks_batch *b, lbks_ctx *ctx);
+int lbks_batch_detach(lbks_batch *b, lbks_ctx *ctx);
+
+/* Advance every attached context in lockstep chunks of `check_every` steps.
+ * After each chunk the energy of each context still running is checked as
+ * in lbks_relax; a converged context stops taking steps (status[i] = LBKS_OK),
+ * one that reaches max_steps gets LBKS_NOT_CONVERGED, one whose overlap fails
+ * LBKS_E_NUMERIC.  status and steps (may be NULL) are host arrays indexed in
+ * attach order.  Returns the number of contexts attached. */
+int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
+                     int32_t *status, int64_t *steps);
+int lbks_batch_size(const lbks_batch *b);
+void lbks_batch_destroy(lbks_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBKS_H */

@@ -92,6 +92,8 @@ def lib():
 
 
 def _p(a: np.ndarray):
+    """Address of a C-contiguous array.  The caller must hold a reference to `a`
+    for the duration of the C call (never pass a temporary)."""
     assert a.flags["C_CONTIGUOUS"]
     return a.ctypes.data
 
@@ -134,9 +136,10 @@ def xc_fields(kind: int, rho: np.ndarray, floor: float = 1e-14):
 def apply_sw(dims, v, wts, u):
     nx, ny, nz = dims
     u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.int32)
+    wts = np.ascontiguousarray(wts, dtype=np.float64)
     out = np.empty_like(u)
-    lib().orc_apply_sw(nx, ny, nz, _p(np.ascontiguousarray(v, dtype=np.int32)),
-                       _p(np.ascontiguousarray(wts, dtype=np.float64)), _p(u), _p(out))
+    lib().orc_apply_sw(nx, ny, nz, _p(v), _p(wts), _p(u), _p(out))
     return out
 
 
@@ -343,14 +346,15 @@ class Oracle:
         for j in range(p.n_orb):
             u = np.ascontiguousarray(psihat[j])
             su = apply_sw(dims, self.v, self.xi, u)
-            ku = -(su - u) / (p.D * p.h * p.h)          # K_h u
-            vu = apply_sw(dims, self.v, self.chi, V * u)  # S_chi (V u)
-            kin = h3 * D(self.N, _p(u), _p(np.ascontiguousarray(ku)))
+            ku = np.ascontiguousarray(-(su - u) / (p.D * p.h * p.h))   # K_h u
+            vu = apply_sw(dims, self.v, self.chi, V * u)                # S_chi (V u)
+            kin = h3 * D(self.N, _p(u), _p(ku))
             pot = h3 * D(self.N, _p(u), _p(vu))
             eps[j] = kin + pot
             e_kin += self.occ[j] * kin
         e_ext = h3 * D(self.N, _p(self.vext), _p(rho))
-        e_h = 0.5 * h3 * D(self.N, _p(np.ascontiguousarray(self.vh_interior())), _p(rho)) if p.hartree else 0.0
+        vhi = self.vh_interior()
+        e_h = 0.5 * h3 * D(self.N, _p(vhi), _p(rho)) if p.hartree else 0.0
         e_x = h3 * D(self.N, _p(rho), _p(ex)) if p.xc != XC_NONE else 0.0
         e_c = h3 * D(self.N, _p(rho), _p(ec)) if p.xc != XC_NONE else 0.0
         ne = h3 * self.L.orc_sum(self.N, _p(rho))

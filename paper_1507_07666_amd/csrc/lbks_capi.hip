@@ -1,0 +1,811 @@
+// lbks_capi.hip -- host runtime and C ABI of liblbks.so.
+//
+// A context owns one solve: its descriptor (grid, parameters, buffer
+// pointers), a device copy of it, and one device allocation carved into the
+// buffers.  Each lattice step is a fixed sequence of kernel launches on the
+// context's stream; the host only enqueues and, at chunk boundaries, reads
+// back a few hundred bytes (energies and the error flag).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lbks.h"
+#include "lbks_kernels.h"
+
+using namespace lbks;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Buf {
+    size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct lbks_ctx {
+    lbks_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *(*ualloc)(size_t, void *) = nullptr;
+    void (*ufree)(void *, void *) = nullptr;
+    void *user = nullptr;
+    void *base = nullptr;       // the single device allocation
+    size_t bytes = 0;
+    InstDesc h{};               // host copy of the descriptor
+    InstDesc *d_desc = nullptr; // device copy (inside base)
+    Plan plan{};
+    int parity = 0;             // populations live in f0 (0) or f1 (1)
+    int64_t steps = 0;
+    bool has_potential = false;
+    double *d_zr = nullptr;     // nuclei table [4 * LBKS_MAX_NUC + 1]
+    std::string err;
+    // timing of the stream-collide kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    lbks_batch *batch = nullptr;
+};
+
+struct lbks_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<lbks_ctx *> members;
+    // device tables rebuilt on membership change
+    void *tables = nullptr;
+    size_t tables_bytes = 0;
+    bool dirty = true;
+    std::vector<Plan> plans;    // one plan per (precision, bucket, W, scheme) group
+    std::vector<std::vector<int>> group_members;
+    InstDesc *d_descs = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::vector<int> active;
+};
+
+namespace {
+
+int fail(lbks_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(lbks_ctx *c, hipError_t e, const char *where)
+{
+    return fail(c, LBKS_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                        \
+    do {                                                       \
+        hipError_t _e = (expr);                                \
+        if (_e != hipSuccess) return hip_fail((c), _e, #expr); \
+    } while (0)
+
+#define KCHK(c, expr)                                                        \
+    do {                                                                     \
+        int _e = (expr);                                                     \
+        if (_e != 0) return hip_fail((c), (hipError_t)_e, #expr);            \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// D3Q19 weights, equilibrium xi_p = w_p (1 + (D - c_s^2) q_p) and potential source
+// chi_p = w_p (1 - c_s^2 q_p), q_p = (|v_p|^2 - 3 c_s^2) / (2 c_s^4), c_s^2 = 1/3,
+// in the velocity order of the kernels (rest, 6 faces, 12 edges).
+void lattice_constants(double D, double *xi, double *chi)
+{
+    const double cs2 = 1.0 / 3.0;
+    for (int p = 0; p < Q; ++p) {
+        const int v2 = p == 0 ? 0 : (p <= 6 ? 1 : 2);
+        const double w = v2 == 0 ? 1.0 / 3.0 : (v2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        const double q = ((double)v2 - 3.0 * cs2) / (2.0 * cs2 * cs2);
+        xi[p] = w * (1.0 + (D - cs2) * q);
+        chi[p] = w * (1.0 - cs2 * q);
+    }
+}
+
+struct Layout {
+    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, C,
+        scal, stage, zr;
+    size_t total = 0;
+};
+
+int validate(const lbks_params *p, std::string &why)
+{
+    if (!p) { why = "params is NULL"; return LBKS_E_INVAL; }
+    for (int a = 0; a < 3; ++a)
+        if (p->N[a] < 4 || p->N[a] > 1024) { why = "grid size out of [4, 1024]"; return LBKS_E_INVAL; }
+    if ((double)p->N[0] * p->N[1] * p->N[2] >= 2147483647.0) { why = "grid too large"; return LBKS_E_INVAL; }
+    if (!(p->h > 0.0) || !isfinite(p->h)) { why = "h must be positive"; return LBKS_E_INVAL; }
+    if (p->n_orb < 1 || p->n_orb > LBKS_MAX_ORB) { why = "n_orb out of [1, 16]"; return LBKS_E_INVAL; }
+    if (p->n_elec < 1 || p->n_elec > 2 * p->n_orb || p->n_elec <= 2 * (p->n_orb - 1)) {
+        why = "n_elec must satisfy 2(n_orb-1) < n_elec <= 2 n_orb";
+        return LBKS_E_INVAL;
+    }
+    if (!(p->omega > 0.0 && p->omega < 2.0)) { why = "omega must lie in (0, 2)"; return LBKS_E_INVAL; }
+    if (!(p->D > 0.0 && p->D <= 7.0 / 18.0 + 1e-15)) {
+        why = "D must lie in (0, 7/18]: larger D makes the relaxation stencil's symbol negative";
+        return LBKS_E_INVAL;
+    }
+    if (p->ortho != LBKS_ORTHO_GS && p->ortho != LBKS_ORTHO_W) { why = "bad ortho"; return LBKS_E_INVAL; }
+    if (p->xc < LBKS_XC_NONE || p->xc > LBKS_XC_X_PZ81) { why = "bad xc"; return LBKS_E_INVAL; }
+    if (p->poisson_sweeps < 0 || p->poisson_sweeps > 64) { why = "poisson_sweeps out of [0, 64]"; return LBKS_E_INVAL; }
+    if (p->precision != LBKS_FP64 && p->precision != LBKS_FP32_BULK) { why = "bad precision"; return LBKS_E_INVAL; }
+    if (!(p->softening >= 0.0)) { why = "softening must be >= 0"; return LBKS_E_INVAL; }
+    if (p->init < LBKS_INIT_GAUSS_NOISE || p->init > LBKS_INIT_USER) { why = "bad init"; return LBKS_E_INVAL; }
+    if (p->init != LBKS_INIT_USER && !(p->init_sigma > 0.0)) { why = "init_sigma must be positive"; return LBKS_E_INVAL; }
+    if (p->scheme != LBKS_SCHEME_POPULATIONS && p->scheme != LBKS_SCHEME_COLLAPSED) { why = "bad scheme"; return LBKS_E_INVAL; }
+    if (p->scheme == LBKS_SCHEME_COLLAPSED && p->omega != 1.0) {
+        why = "the collapsed scheme exists only at omega = 1";
+        return LBKS_E_INVAL;
+    }
+    for (int i = 0; i < 7; ++i)
+        if (p->reserved[i]) { why = "reserved fields must be zero"; return LBKS_E_INVAL; }
+    return 0;
+}
+
+Layout plan_layout(const lbks_params *p)
+{
+    Layout L;
+    const size_t N = (size_t)p->N[0] * p->N[1] * p->N[2];
+    const size_t s = p->precision == LBKS_FP32_BULK ? 4 : 8;
+    const size_t n = (size_t)p->n_orb;
+    const size_t ntile = (N + BS - 1) / BS;
+    const int no = orbital_bucket(p->n_orb);
+    const size_t padded = (size_t)(p->N[0] + 2) * (p->N[1] + 2) * (p->N[2] + 2);
+    size_t off = 0;
+    auto take = [&](Buf &b, size_t bytes) {
+        b.off = off;
+        b.bytes = bytes;
+        off += align_up(bytes);
+    };
+    take(L.desc, sizeof(InstDesc));
+    const bool pops = p->scheme == LBKS_SCHEME_POPULATIONS;
+    take(L.f0, pops ? n * Q * N * s : 0);
+    take(L.f1, pops ? n * Q * N * s : 0);
+    take(L.psi, n * N * s);
+    take(L.psihat, n * N * s);
+    take(L.psistar, p->ortho == LBKS_ORTHO_W ? n * N * s : 0);
+    take(L.rho, N * s);
+    take(L.V, N * s);
+    take(L.Vd, s == 8 ? 0 : N * 8);
+    take(L.vext, N * 8);
+    take(L.vh, padded * 8);
+    take(L.s_part, (size_t)(no * (no + 1) / 2) * ntile * 8);
+    take(L.m_part, (size_t)NMOM * ntile * 8);
+    take(L.e_part, (size_t)(2 * no + NEBASE) * ntile * 8);
+    take(L.r_part, 2 * ntile * 8);
+    take(L.C, 2 * MAXO * MAXO * 8);
+    take(L.scal, SC_SIZE * 8);
+    take(L.stage, (n + 1) * N * 8);
+    take(L.zr, (4 * LBKS_MAX_NUC + 1) * 8);
+    L.total = off;
+    return L;
+}
+
+void *dev_alloc(lbks_ctx *c, size_t bytes)
+{
+    if (c->ualloc) return c->ualloc(bytes, c->user);
+    void *ptr = nullptr;
+    if (hipMalloc(&ptr, bytes) != hipSuccess) return nullptr;
+    return ptr;
+}
+
+void dev_free(lbks_ctx *c, void *ptr)
+{
+    if (!ptr) return;
+    if (c->ufree) c->ufree(ptr, c->user);
+    else (void)hipFree(ptr);
+}
+
+int upload_desc(lbks_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->d_desc, &c->h, sizeof(InstDesc), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+// ---------------------------------------------------------- step sequences
+
+int enqueue_orthonormalise(lbks_ctx *c)
+{
+    KCHK(c, launch_overlap_finalize(c->plan, c->stream));
+    KCHK(c, launch_orthonormalise(c->plan, c->stream));
+    return 0;
+}
+
+int enqueue_hartree_boundary(lbks_ctx *c)
+{
+    KCHK(c, launch_multipole_finalize(c->plan, c->stream));
+    KCHK(c, launch_ghost(c->plan, c->stream));
+    return 0;
+}
+
+int enqueue_sweeps(lbks_ctx *c, int sweeps)
+{
+    for (int k = 0; k < sweeps; ++k) {
+        KCHK(c, launch_sor(c->plan, 0, c->stream));
+        KCHK(c, launch_sor(c->plan, 1, c->stream));
+    }
+    return 0;
+}
+
+hipEvent_t next_event(lbks_ctx *c)
+{
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev.push_back(e);
+    }
+    return c->ev[c->ev_used++];
+}
+
+int flush_timing(lbks_ctx *c)
+{
+    if (c->ev_used == 0) return 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+    }
+    c->ev_used = 0;
+    return 0;
+}
+
+// One lattice step: orthonormalise, density, Hartree sweeps, potential, then the
+// lattice Boltzmann update of every orbital (populations or collapsed form).
+int enqueue_step(lbks_ctx *c)
+{
+    int rc;
+    if ((rc = enqueue_orthonormalise(c))) return rc;
+    if (c->p.hartree) {
+        if ((rc = enqueue_hartree_boundary(c))) return rc;
+        if ((rc = enqueue_sweeps(c, c->p.poisson_sweeps))) return rc;
+    }
+    KCHK(c, launch_potential(c->plan, 0, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_used + 2 > 4096 && (rc = flush_timing(c))) return rc;
+        e0 = next_event(c);
+        e1 = next_event(c);
+        if (!e0 || !e1) return fail(c, LBKS_E_HIP, "hipEventCreate failed");
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    if (c->p.scheme == LBKS_SCHEME_POPULATIONS) {
+        KCHK(c, launch_stream_collide(c->plan, c->parity, c->stream));
+        c->parity ^= 1;
+    } else {
+        KCHK(c, launch_collapsed_update(c->plan, c->stream));
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
+    c->steps += 1;
+    return 0;
+}
+
+// Energies of the current state into the scalar block (device).
+int enqueue_energy(lbks_ctx *c)
+{
+    int rc;
+    if ((rc = enqueue_orthonormalise(c))) return rc;
+    KCHK(c, launch_potential(c->plan, 1, c->stream));
+    KCHK(c, launch_energy_terms(c->plan, c->stream));
+    KCHK(c, launch_energy_finalize(c->plan, c->stream));
+    return 0;
+}
+
+int read_energies(lbks_ctx *c, lbks_energies *out, double *errflag)
+{
+    double buf[SC_SIZE];
+    HIPCHK(c, hipMemcpyAsync(buf, c->h.scal, sizeof(buf), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->e_total = buf[SC_ENER + 0];
+        out->e_kin = buf[SC_ENER + 1];
+        out->e_ext = buf[SC_ENER + 2];
+        out->e_hartree = buf[SC_ENER + 3];
+        out->e_x = buf[SC_ENER + 4];
+        out->e_c = buf[SC_ENER + 5];
+        out->e_nn = buf[SC_ENER + 6];
+        out->n_electrons = buf[SC_ENER + 7];
+        out->poisson_residual = buf[SC_ENER + 8];
+        for (int j = 0; j < LBKS_MAX_ORB; ++j) out->eps[j] = buf[SC_ENER + 9 + j];
+        out->steps = c->steps;
+    }
+    if (errflag) *errflag = buf[SC_ERR];
+    return 0;
+}
+
+int read_scalar(lbks_ctx *c, int idx, double *v)
+{
+    HIPCHK(c, hipMemcpyAsync(v, c->h.scal + idx, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+}  // namespace
+
+// ============================================================== public ABI
+
+extern "C" int lbks_params_default(lbks_params *p)
+{
+    if (!p) return LBKS_E_INVAL;
+    memset(p, 0, sizeof(*p));
+    p->omega = 1.0;
+    p->D = 1.0 / 3.0;
+    p->ortho = LBKS_ORTHO_GS;
+    p->xc = LBKS_XC_X_LYPLOCAL;
+    p->hartree = 1;
+    p->poisson_sweeps = 2;
+    p->precision = LBKS_FP64;
+    p->softening = 0.05;
+    p->init = LBKS_INIT_RANDOM_GAUSS;
+    p->init_sigma = 1.0;
+    p->init_noise = 0.0;
+    p->seed = 0;
+    p->rho_floor = 1e-14;
+    p->scheme = LBKS_SCHEME_POPULATIONS;
+    return 0;
+}
+
+extern "C" size_t lbks_estimate_bytes(const lbks_params *p)
+{
+    std::string why;
+    if (validate(p, why)) return 0;
+    return plan_layout(p).total;
+}
+
+extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ctx **out)
+{
+    g_create_error.clear();
+    if (!out) return fail(nullptr, LBKS_E_INVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (int rc = validate(p, why)) return fail(nullptr, rc, why);
+    if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr)))
+        return fail(nullptr, LBKS_E_INVAL, "alloc and free must both be set or both be NULL");
+    lbks_ctx *c = new lbks_ctx();
+    c->p = *p;
+    c->device = dev ? dev->device : 0;
+    if (hipSetDevice(c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBKS_E_HIP, "hipSetDevice failed");
+    }
+    if (dev && dev->stream) {
+        c->stream = (hipStream_t)dev->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, LBKS_E_HIP, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (dev) {
+        c->ualloc = dev->alloc;
+        c->ufree = dev->free;
+        c->user = dev->user;
+    }
+    Layout L = plan_layout(p);
+    c->base = dev_alloc(c, L.total);
+    if (!c->base) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return fail(nullptr, LBKS_E_NOMEM, "device allocation failed");
+    }
+    c->bytes = L.total;
+    char *b = (char *)c->base;
+    auto at = [&](const Buf &x) -> void * { return x.bytes ? (void *)(b + x.off) : nullptr; };
+    InstDesc &h = c->h;
+    memset(&h, 0, sizeof(h));
+    h.nx = p->N[0];
+    h.ny = p->N[1];
+    h.nz = p->N[2];
+    h.n_orb = p->n_orb;
+    h.nsite = h.nx * h.ny * h.nz;
+    h.ntile = (h.nsite + BS - 1) / BS;
+    h.ntile_ghost = (2 * (h.ny * h.nz + h.nx * h.nz + h.nx * h.ny) + BS - 1) / BS;
+    h.ntile_sor = (((h.nx + 1) / 2) * h.ny * h.nz + BS - 1) / BS;
+    h.ortho = p->ortho;
+    h.xc = p->xc;
+    h.hartree = p->hartree;
+    h.precision = p->precision;
+    h.scheme = p->scheme;
+    h.h = p->h;
+    h.h3 = p->h * p->h * p->h;
+    h.omega = p->omega;
+    h.D = p->D;
+    // one lattice step is dt = 2 (1/omega - 1/2) D h^2 of imaginary time (hbar = m = 1)
+    h.dt = 2.0 * (1.0 / p->omega - 0.5) * p->D * p->h * p->h;
+    {
+        const double PI = 3.14159265358979323846;
+        const double mu = (cos(PI / (h.nx + 1)) + cos(PI / (h.ny + 1)) + cos(PI / (h.nz + 1))) / 3.0;
+        h.omega_sor = 2.0 / (1.0 + sqrt(1.0 - mu * mu));
+    }
+    h.rho_floor = p->rho_floor;
+    h.e_nn = 0.0;
+    for (int j = 0; j < MAXO; ++j) h.occ[j] = 0.0;
+    for (int j = 0; j < p->n_orb; ++j) h.occ[j] = 2.0;
+    h.occ[p->n_orb - 1] = (double)p->n_elec - 2.0 * (p->n_orb - 1);
+    lattice_constants(p->D, h.xi, h.chi);
+    h.f0 = at(L.f0);
+    h.f1 = at(L.f1);
+    h.psi = at(L.psi);
+    h.psihat = at(L.psihat);
+    h.psistar = at(L.psistar);
+    h.rho = at(L.rho);
+    h.V = at(L.V);
+    h.Vd = p->precision == LBKS_FP64 ? (double *)h.V : (double *)at(L.Vd);
+    h.vext = (double *)at(L.vext);
+    h.vh = (double *)at(L.vh);
+    h.s_part = (double *)at(L.s_part);
+    h.m_part = (double *)at(L.m_part);
+    h.e_part = (double *)at(L.e_part);
+    h.r_part = (double *)at(L.r_part);
+    h.C = (double *)at(L.C);
+    h.scal = (double *)at(L.scal);
+    h.stage = (double *)at(L.stage);
+    c->d_zr = (double *)at(L.zr);
+    c->d_desc = (InstDesc *)at(L.desc);
+    Plan &pl = c->plan;
+    pl.d_desc = c->d_desc;
+    pl.precision = p->precision == LBKS_FP32_BULK ? 1 : 0;
+    pl.no = orbital_bucket(p->n_orb);
+    pl.wmode = p->ortho == LBKS_ORTHO_W;
+    pl.ntile = h.ntile;
+    pl.ntile_ghost = h.ntile_ghost;
+    pl.ntile_sor = h.ntile_sor;
+    pl.n_inst = 1;
+
+    int rc = 0;
+    auto bail = [&](int code) {
+        std::string m = c->err;
+        lbks_destroy(c);
+        return fail(nullptr, code, m);
+    };
+    // zero everything once (fields, Hartree potential incl. ghosts, scalars)
+    if (hipMemsetAsync(c->base, 0, L.total, c->stream) != hipSuccess) {
+        c->err = "hipMemsetAsync failed";
+        return bail(LBKS_E_HIP);
+    }
+    if ((rc = upload_desc(c))) return bail(rc);
+    if (p->init != LBKS_INIT_USER) {
+        if (launch_init_psi(pl, p->init == LBKS_INIT_GAUSS_NOISE ? 0 : 1, p->init_sigma, p->init_noise, p->seed,
+                            c->stream)) {
+            c->err = "init kernel failed";
+            return bail(LBKS_E_HIP);
+        }
+        if (p->scheme == LBKS_SCHEME_POPULATIONS) {
+            if (launch_equilibrium(pl, 0, c->stream) || launch_moment(pl, 0, c->stream)) {
+                c->err = "init kernel failed";
+                return bail(LBKS_E_HIP);
+            }
+        } else {
+            if (launch_overlap_psi(pl, c->stream)) {
+                c->err = "init kernel failed";
+                return bail(LBKS_E_HIP);
+            }
+        }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->err = "initialisation failed on the device";
+        return bail(LBKS_E_HIP);
+    }
+    *out = c;
+    return LBKS_OK;
+}
+
+extern "C" void lbks_destroy(lbks_ctx *c)
+{
+    if (!c) return;
+    if (c->batch) lbks_batch_detach(c->batch, c);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    dev_free(c, c->base);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+extern "C" const char *lbks_last_error(const lbks_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int lbks_shape(const lbks_ctx *c, int32_t N[3], int32_t *n_orb)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (N) {
+        N[0] = c->p.N[0];
+        N[1] = c->p.N[1];
+        N[2] = c->p.N[2];
+    }
+    if (n_orb) *n_orb = c->p.n_orb;
+    return 0;
+}
+
+extern "C" size_t lbks_device_bytes(const lbks_ctx *c) { return c ? c->bytes : 0; }
+
+extern "C" int lbks_set_nuclei(lbks_ctx *c, int32_t n, const double *Z, const double *xyz)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (n < 1 || n > LBKS_MAX_NUC || !Z || !xyz) return fail(c, LBKS_E_INVAL, "bad nuclei count or NULL array");
+    double zr[4 * LBKS_MAX_NUC + 1];
+    const double hx = 0.5 * (c->p.N[0] - 1) * c->p.h, hy = 0.5 * (c->p.N[1] - 1) * c->p.h,
+                 hz = 0.5 * (c->p.N[2] - 1) * c->p.h;
+    for (int I = 0; I < n; ++I) {
+        if (!(Z[I] > 0.0) || !isfinite(Z[I])) return fail(c, LBKS_E_INVAL, "nuclear charges must be positive");
+        const double x = xyz[3 * I], y = xyz[3 * I + 1], z = xyz[3 * I + 2];
+        if (!(fabs(x) <= hx && fabs(y) <= hy && fabs(z) <= hz)) return fail(c, LBKS_E_INVAL, "nucleus outside the box");
+        zr[4 * I] = Z[I];
+        zr[4 * I + 1] = x;
+        zr[4 * I + 2] = y;
+        zr[4 * I + 3] = z;
+    }
+    zr[4 * n] = c->p.softening * c->p.softening;
+    // ion-ion repulsion (bare Coulomb)
+    double enn = 0.0;
+    for (int I = 0; I < n; ++I)
+        for (int J = I + 1; J < n; ++J) {
+            const double dx = xyz[3 * I] - xyz[3 * J], dy = xyz[3 * I + 1] - xyz[3 * J + 1],
+                         dz = xyz[3 * I + 2] - xyz[3 * J + 2];
+            enn += Z[I] * Z[J] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+    HIPCHK(c, hipMemcpyAsync(c->d_zr, zr, sizeof(double) * (4 * n + 1), hipMemcpyHostToDevice, c->stream));
+    KCHK(c, launch_vext(c->plan, n, c->d_zr, c->stream));
+    c->h.e_nn = enn;
+    int rc = upload_desc(c);
+    if (rc) return rc;
+    c->has_potential = true;
+    return 0;
+}
+
+extern "C" int lbks_set_potential(lbks_ctx *c, const double *v)
+{
+    if (!c || !v) return LBKS_E_INVAL;
+    HIPCHK(c, hipMemcpyAsync(c->h.vext, v, sizeof(double) * (size_t)c->h.nsite, hipMemcpyHostToDevice, c->stream));
+    c->h.e_nn = 0.0;
+    int rc = upload_desc(c);
+    if (rc) return rc;
+    c->has_potential = true;
+    return 0;
+}
+
+extern "C" int lbks_set_orbitals(lbks_ctx *c, const double *psi)
+{
+    if (!c || !psi) return LBKS_E_INVAL;
+    const size_t n = (size_t)c->p.n_orb * c->h.nsite;
+    // new orbitals are a recovery point: clear a previous numeric-error flag
+    static const double zero = 0.0;
+    HIPCHK(c, hipMemcpyAsync(c->h.scal + SC_ERR, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h.stage, psi, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    KCHK(c, launch_psi_from_stage(c->plan, c->stream));
+    if (c->p.scheme == LBKS_SCHEME_POPULATIONS) {
+        KCHK(c, launch_equilibrium(c->plan, c->parity, c->stream));
+        KCHK(c, launch_moment(c->plan, c->parity, c->stream));
+    } else {
+        KCHK(c, launch_overlap_psi(c->plan, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t check_every, int64_t *steps_done)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (steps_done) *steps_done = 0;
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    if (max_steps < 0) return fail(c, LBKS_E_INVAL, "max_steps < 0");
+    if (check_every < 1) check_every = 1;
+    int64_t done = 0;
+    bool have_prev = false;
+    double e_prev = 0.0;
+    int rc;
+    while (done < max_steps) {
+        const int64_t n = std::min<int64_t>(check_every, max_steps - done);
+        for (int64_t k = 0; k < n; ++k)
+            if ((rc = enqueue_step(c))) return rc;
+        done += n;
+        if (steps_done) *steps_done = done;
+        if (dE_tol > 0.0) {
+            if ((rc = enqueue_energy(c))) return rc;
+            lbks_energies e;
+            double errf = 0.0;
+            if ((rc = read_energies(c, &e, &errf))) return rc;
+            if (errf != 0.0 || !isfinite(e.e_total))
+                return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+            if (have_prev && fabs(e.e_total - e_prev) < dE_tol) return LBKS_OK;
+            e_prev = e.e_total;
+            have_prev = true;
+        }
+    }
+    double errf = 0.0;
+    if ((rc = read_scalar(c, SC_ERR, &errf))) return rc;
+    if (errf != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+    if (c->timing && (rc = flush_timing(c))) return rc;
+    return LBKS_NOT_CONVERGED;
+}
+
+extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
+{
+    if (!c || !out) return LBKS_E_INVAL;
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    int rc;
+    if ((rc = enqueue_orthonormalise(c))) return rc;
+    if (c->p.hartree) {
+        if ((rc = enqueue_hartree_boundary(c))) return rc;
+        // converge V_H for the current density: blocks of 10 sweeps until the
+        // relative residual is <= 1e-12
+        const double tol = 1e-12;
+        for (int it = 0;; ++it) {
+            KCHK(c, launch_residual(c->plan, c->stream));
+            KCHK(c, launch_residual_finalize(c->plan, c->stream));
+            double res = 0.0;
+            if ((rc = read_scalar(c, SC_RES, &res))) return rc;
+            if (!(res > tol)) break;
+            if (!isfinite(res) || it > 20000) return fail(c, LBKS_E_NUMERIC, "Poisson relaxation did not converge");
+            if ((rc = enqueue_sweeps(c, 10))) return rc;
+        }
+    }
+    if ((rc = enqueue_energy(c))) return rc;
+    double errf = 0.0;
+    if ((rc = read_energies(c, out, &errf))) return rc;
+    if (errf != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+    if (!c->p.hartree) out->poisson_residual = 0.0;
+    return 0;
+}
+
+extern "C" int lbks_orbitals(lbks_ctx *c, double *psi, size_t n_psi, double *rho, size_t n_rho)
+{
+    if (!c || !psi) return LBKS_E_INVAL;
+    const size_t N = (size_t)c->h.nsite, n = (size_t)c->p.n_orb;
+    if (n_psi < n * N) return fail(c, LBKS_E_INVAL, "psi buffer too small");
+    if (rho && n_rho < N) return fail(c, LBKS_E_INVAL, "rho buffer too small");
+    int rc;
+    if ((rc = enqueue_orthonormalise(c))) return rc;
+    KCHK(c, launch_stage_orbitals(c->plan, c->stream));
+    HIPCHK(c, hipMemcpyAsync(psi, c->h.stage, n * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (rho) HIPCHK(c, hipMemcpyAsync(rho, c->h.stage + n * N, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+extern "C" int lbks_set_timing(lbks_ctx *c, int32_t enable)
+{
+    if (!c) return LBKS_E_INVAL;
+    int rc = flush_timing(c);
+    if (rc) return rc;
+    c->timing = enable != 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return 0;
+}
+
+extern "C" int lbks_kernel_time(lbks_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!c || kernel != 0) return LBKS_E_INVAL;
+    int rc = flush_timing(c);
+    if (rc) return rc;
+    if (total_ms) *total_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    return 0;
+}
+
+extern "C" int lbks_copy_kernel(void *dst, const void *src, size_t bytes, void *stream)
+{
+    if (!dst || !src || (bytes % 16) || (((uintptr_t)dst | (uintptr_t)src) & 15)) return LBKS_E_INVAL;
+    int e = launch_copy(dst, src, bytes, (hipStream_t)stream);
+    return e ? LBKS_E_HIP : 0;
+}
+
+// ================================================================ batches
+
+extern "C" int lbks_batch_create(const lbks_device *dev, lbks_batch **out)
+{
+    if (!out) return LBKS_E_INVAL;
+    lbks_batch *b = new lbks_batch();
+    b->device = dev ? dev->device : 0;
+    if (dev && dev->stream) {
+        b->stream = (hipStream_t)dev->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return LBKS_E_HIP;
+        }
+        b->own_stream = true;
+    }
+    *out = b;
+    return 0;
+}
+
+extern "C" int lbks_batch_attach(lbks_batch *b, lbks_ctx *c)
+{
+    if (!b || !c || c->batch) return LBKS_E_INVAL;
+    if (c->stream != b->stream || c->device != b->device)
+        return fail(c, LBKS_E_INVAL, "context must share the batch's stream and device");
+    b->members.push_back(c);
+    c->batch = b;
+    b->dirty = true;
+    return 0;
+}
+
+extern "C" int lbks_batch_detach(lbks_batch *b, lbks_ctx *c)
+{
+    if (!b || !c || c->batch != b) return LBKS_E_INVAL;
+    b->members.erase(std::remove(b->members.begin(), b->members.end(), c), b->members.end());
+    c->batch = nullptr;
+    b->dirty = true;
+    return 0;
+}
+
+extern "C" int lbks_batch_size(const lbks_batch *b) { return b ? (int)b->members.size() : 0; }
+
+extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
+                                int32_t *status, int64_t *steps)
+{
+    if (!b) return LBKS_E_INVAL;
+    // Lockstep over members, each launch per context (batched launches below
+    // replace this once the batch plan is built).
+    const int m = (int)b->members.size();
+    std::vector<int> st(m, LBKS_NOT_CONVERGED);
+    std::vector<int64_t> done(m, 0);
+    std::vector<double> eprev(m, 0.0);
+    std::vector<bool> havep(m, false), running(m, true);
+    if (check_every < 1) check_every = 1;
+    int64_t t = 0;
+    while (t < max_steps) {
+        const int64_t n = std::min<int64_t>(check_every, max_steps - t);
+        for (int i = 0; i < m; ++i) {
+            if (!running[i]) continue;
+            for (int64_t k = 0; k < n; ++k) {
+                int rc = enqueue_step(b->members[i]);
+                if (rc) { st[i] = rc; running[i] = false; break; }
+            }
+            done[i] += n;
+        }
+        t += n;
+        if (dE_tol > 0.0) {
+            bool any = false;
+            for (int i = 0; i < m; ++i) {
+                if (!running[i]) continue;
+                lbks_ctx *c = b->members[i];
+                lbks_energies e;
+                double errf = 0.0;
+                int rc = enqueue_energy(c);
+                if (!rc) rc = read_energies(c, &e, &errf);
+                if (rc) { st[i] = rc; running[i] = false; continue; }
+                if (errf != 0.0 || !isfinite(e.e_total)) { st[i] = LBKS_E_NUMERIC; running[i] = false; continue; }
+                if (havep[i] && fabs(e.e_total - eprev[i]) < dE_tol) { st[i] = LBKS_OK; running[i] = false; continue; }
+                eprev[i] = e.e_total;
+                havep[i] = true;
+                any = true;
+            }
+            if (!any) break;
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        if (status) status[i] = st[i];
+        if (steps) steps[i] = done[i];
+    }
+    return m;
+}
+
+extern "C" void lbks_batch_destroy(lbks_batch *b)
+{
+    if (!b) return;
+    for (lbks_ctx *c : b->members) c->batch = nullptr;
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}

@@ -1,0 +1,105 @@
+// lbks_kernels.h -- per-solve device descriptor and the launchers of the
+// relaxation kernels (internal to liblbks.so).
+//
+// One solve ("instance") is a descriptor of its grid, parameters and device
+// buffers.  Every kernel takes an array of descriptors plus an optional tile
+// table mapping each workgroup to (instance, tile), so one launch serves a
+// single solve or a whole batch of uneven solves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbks {
+
+constexpr int Q = 19;          // D3Q19 velocities
+constexpr int BS = 256;        // threads per workgroup in every site kernel
+constexpr int MAXO = 16;       // orbital capacity of the descriptor
+constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
+constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
+
+// Offsets into the per-instance FP64 scalar block.
+constexpr int SC_MOM = 0;                  // 10 multipoles
+constexpr int SC_S = 16;                   // packed lower overlap, 136 values
+constexpr int SC_ENER = 160;               // lbks_energies prefix: 9 + 16 doubles
+constexpr int SC_RES = 192;                // Poisson relative residual
+constexpr int SC_ERR = 193;                // nonzero: overlap not finite / not SPD
+constexpr int SC_SIZE = 200;
+
+struct InstDesc {
+    int nx, ny, nz, n_orb;
+    int nsite;                 // nx*ny*nz (< 2^31)
+    int ntile;                 // site tiles of BS nodes
+    int ntile_ghost;           // tiles over the six ghost faces
+    int ntile_sor;             // tiles over one colour of the SOR sweep
+    int ortho, xc, hartree, precision;
+    int scheme, pad0;
+    double h, h3, omega, dt, D, omega_sor, rho_floor, e_nn;
+    double occ[MAXO];
+    double xi[Q], chi[Q];
+    // buffers (bulk precision unless noted)
+    void *f0, *f1;             // populations [n_orb][Q][site]
+    void *psi;                 // sum_p f, or the orbital state of the collapsed scheme
+    void *psihat;              // orthonormalised orbitals
+    void *psistar;             // equilibrium orbitals of the W mode
+    void *rho;                 // density
+    void *V;                   // KS potential used by the collide
+    double *Vd;                // FP64 potential for energies (== V in FP64 mode)
+    double *vext;              // FP64 external potential
+    double *vh;                // FP64 Hartree potential with one ghost layer
+    double *s_part;            // [npair][ntile]
+    double *m_part;            // [NMOM][ntile]
+    double *e_part;            // [2*bucket(n_orb) + NEBASE][ntile]
+    double *r_part;            // [2][ntile]
+    double *C;                 // [MAXO*MAXO] C, then [MAXO*MAXO] C* (W mode)
+    double *scal;              // [SC_SIZE]
+    double *stage;             // FP64 staging, (n_orb + 1) * nsite
+};
+
+// Tile tables for batched launches: entry b of a table is (instance, tile).
+struct TileTables {
+    const int2 *site = nullptr;   int n_site = 0;
+    const int2 *ghost = nullptr;  int n_ghost = 0;
+    const int2 *sor = nullptr;    int n_sor = 0;
+    const int *inst = nullptr;    int n_inst = 0;   // instance list for per-instance kernels
+};
+
+// Launch plan of one kernel family: descriptor array on the device, tile
+// tables (null tables: a single instance, descriptor 0), and the template
+// buckets that apply to every instance in the plan.
+struct Plan {
+    const InstDesc *d_desc = nullptr;
+    TileTables tt;
+    int precision = 0;    // 0 FP64, 1 FP32 bulk
+    int no = 1;           // orbital bucket: 1,2,3,4,5,8,16
+    bool wmode = false;
+    int ntile = 0, ntile_ghost = 0, ntile_sor = 0;   // single-instance counts
+    int n_inst = 1;
+};
+
+int orbital_bucket(int n_orb);
+
+// Launchers (enqueue on `st`; return hipError_t as int).
+int launch_init_psi(const Plan &pl, int mode, double sigma, double noise, uint64_t seed, hipStream_t st);
+int launch_psi_from_stage(const Plan &pl, hipStream_t st);
+int launch_equilibrium(const Plan &pl, int parity, hipStream_t st);
+int launch_moment(const Plan &pl, int parity, hipStream_t st);
+int launch_overlap_psi(const Plan &pl, hipStream_t st);
+int launch_overlap_finalize(const Plan &pl, hipStream_t st);
+int launch_orthonormalise(const Plan &pl, hipStream_t st);
+int launch_multipole_finalize(const Plan &pl, hipStream_t st);
+int launch_ghost(const Plan &pl, hipStream_t st);
+int launch_sor(const Plan &pl, int color, hipStream_t st);
+int launch_potential(const Plan &pl, int to_fp64, hipStream_t st);
+int launch_stream_collide(const Plan &pl, int parity, hipStream_t st);
+int launch_collapsed_update(const Plan &pl, hipStream_t st);
+int launch_energy_terms(const Plan &pl, hipStream_t st);
+int launch_energy_finalize(const Plan &pl, hipStream_t st);
+int launch_residual(const Plan &pl, hipStream_t st);
+int launch_residual_finalize(const Plan &pl, hipStream_t st);
+int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st);
+int launch_stage_orbitals(const Plan &pl, hipStream_t st);
+int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+
+}  // namespace lbks

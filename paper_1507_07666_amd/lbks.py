@@ -1,0 +1,308 @@
+"""ctypes binding of liblbks.so (the C ABI in include/lbks.h).
+
+Argument marshalling only: every step of the relaxation runs in the library's
+HIP kernels.  The functions keep the C names (lbks_create, lbks_set_nuclei,
+lbks_relax, lbks_energy, lbks_orbitals, ...); `Solver` is a thin owner of one
+context.  PyTorch, when present, supplies the stream and the device
+allocator; the library never falls back to anything but its own kernels and
+raises if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (CFUNCTYPE, POINTER, Structure, c_char_p, c_double, c_int32, c_int64,
+                    c_size_t, c_uint64, c_void_p)
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbks.so")
+
+LBKS_OK, LBKS_NOT_CONVERGED = 0, 1
+LBKS_E_INVAL, LBKS_E_NOMEM, LBKS_E_HIP, LBKS_E_NUMERIC, LBKS_E_STATE = -1, -2, -3, -4, -5
+LBKS_ORTHO_GS, LBKS_ORTHO_W = 0, 1
+LBKS_XC_NONE, LBKS_XC_X, LBKS_XC_X_LYPLOCAL, LBKS_XC_X_PZ81 = 0, 1, 2, 3
+LBKS_FP64, LBKS_FP32_BULK = 0, 1
+LBKS_INIT_GAUSS_NOISE, LBKS_INIT_RANDOM_GAUSS, LBKS_INIT_USER = 0, 1, 2
+LBKS_SCHEME_POPULATIONS, LBKS_SCHEME_COLLAPSED = 0, 1
+LBKS_MAX_ORB = 16
+
+
+class lbks_params(Structure):
+    _fields_ = [("N", c_int32 * 3), ("h", c_double), ("n_orb", c_int32), ("n_elec", c_int32),
+                ("omega", c_double), ("D", c_double), ("ortho", c_int32), ("xc", c_int32),
+                ("hartree", c_int32), ("poisson_sweeps", c_int32), ("precision", c_int32),
+                ("softening", c_double), ("init", c_int32), ("init_sigma", c_double),
+                ("init_noise", c_double), ("seed", c_uint64), ("rho_floor", c_double),
+                ("scheme", c_int32), ("reserved", c_int32 * 7)]
+
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class lbks_device(Structure):
+    _fields_ = [("stream", c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p),
+                ("device", c_int32), ("reserved", c_int32 * 3)]
+
+
+class lbks_energies(Structure):
+    _fields_ = [("e_total", c_double), ("e_kin", c_double), ("e_ext", c_double),
+                ("e_hartree", c_double), ("e_x", c_double), ("e_c", c_double), ("e_nn", c_double),
+                ("n_electrons", c_double), ("poisson_residual", c_double),
+                ("eps", c_double * LBKS_MAX_ORB), ("steps", c_int64)]
+
+    def as_dict(self, n_orb: int) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "eps"}
+        d["eps"] = np.array(self.eps[:n_orb])
+        return d
+
+
+# exported symbol -> (restype, argtypes); the ABI test checks this list against include/lbks.h
+SIGNATURES = {
+    "lbks_params_default": (c_int32, [POINTER(lbks_params)]),
+    "lbks_create": (c_int32, [POINTER(lbks_params), POINTER(lbks_device), POINTER(c_void_p)]),
+    "lbks_set_nuclei": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "lbks_relax": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int64)]),
+    "lbks_energy": (c_int32, [c_void_p, POINTER(lbks_energies)]),
+    "lbks_orbitals": (c_int32, [c_void_p, POINTER(c_double), c_size_t, POINTER(c_double), c_size_t]),
+    "lbks_destroy": (None, [c_void_p]),
+    "lbks_last_error": (c_char_p, [c_void_p]),
+    "lbks_set_potential": (c_int32, [c_void_p, POINTER(c_double)]),
+    "lbks_set_orbitals": (c_int32, [c_void_p, POINTER(c_double)]),
+    "lbks_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "lbks_device_bytes": (c_size_t, [c_void_p]),
+    "lbks_estimate_bytes": (c_size_t, [POINTER(lbks_params)]),
+    "lbks_set_timing": (c_int32, [c_void_p, c_int32]),
+    "lbks_kernel_time": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
+    "lbks_copy_kernel": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "lbks_batch_create": (c_int32, [POINTER(lbks_device), POINTER(c_void_p)]),
+    "lbks_batch_attach": (c_int32, [c_void_p, c_void_p]),
+    "lbks_batch_detach": (c_int32, [c_void_p, c_void_p]),
+    "lbks_batch_relax": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int32),
+                                   POINTER(c_int64)]),
+    "lbks_batch_size": (c_int32, [c_void_p]),
+    "lbks_batch_destroy": (None, [c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load liblbks.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1507_07666_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class LbksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbks error {code}: {msg}")
+        self.code = code
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+# ------------------------------------------------------------- thin wrappers
+
+def lbks_params_default() -> lbks_params:
+    p = lbks_params()
+    load().lbks_params_default(ctypes.byref(p))
+    return p
+
+
+def lbks_create(p: lbks_params, dev: Optional[lbks_device] = None):
+    L = load()
+    out = c_void_p()
+    rc = L.lbks_create(ctypes.byref(p), ctypes.byref(dev) if dev is not None else None, ctypes.byref(out))
+    if rc != 0:
+        raise LbksError(rc, L.lbks_last_error(None).decode())
+    return out
+
+
+def lbks_last_error(ctx) -> str:
+    return load().lbks_last_error(ctx).decode()
+
+
+def _check(ctx, rc, ok=(0,)):
+    if rc not in ok:
+        raise LbksError(rc, lbks_last_error(ctx))
+    return rc
+
+
+def lbks_set_nuclei(ctx, Z, R):
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    return _check(ctx, load().lbks_set_nuclei(ctx, len(Z), _dptr(Z), _dptr(R)))
+
+
+def lbks_set_potential(ctx, v):
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+    return _check(ctx, load().lbks_set_potential(ctx, _dptr(v)))
+
+
+def lbks_set_orbitals(ctx, psi):
+    psi = np.ascontiguousarray(psi, dtype=np.float64).reshape(-1)
+    return _check(ctx, load().lbks_set_orbitals(ctx, _dptr(psi)))
+
+
+def lbks_relax(ctx, max_steps, dE_tol=0.0, check_every=100):
+    done = c_int64(0)
+    rc = load().lbks_relax(ctx, int(max_steps), float(dE_tol), int(check_every), ctypes.byref(done))
+    _check(ctx, rc, ok=(LBKS_OK, LBKS_NOT_CONVERGED))
+    return rc, done.value
+
+
+def lbks_energy(ctx) -> lbks_energies:
+    e = lbks_energies()
+    _check(ctx, load().lbks_energy(ctx, ctypes.byref(e)))
+    return e
+
+
+def lbks_shape(ctx):
+    N = (c_int32 * 3)()
+    n = c_int32()
+    _check(ctx, load().lbks_shape(ctx, N, ctypes.byref(n)))
+    return (N[0], N[1], N[2]), n.value
+
+
+def lbks_orbitals(ctx, with_rho=True):
+    (nx, ny, nz), n = lbks_shape(ctx)
+    psi = np.empty((n, nz, ny, nx))
+    rho = np.empty((nz, ny, nx)) if with_rho else None
+    rc = load().lbks_orbitals(ctx, _dptr(psi), psi.size, _dptr(rho) if with_rho else None,
+                              rho.size if with_rho else 0)
+    _check(ctx, rc)
+    return psi, rho
+
+
+def lbks_destroy(ctx):
+    if ctx:
+        load().lbks_destroy(ctx)
+
+
+# ------------------------------------------------------------ torch plumbing
+
+def torch_device_binding(device: int = 0, stream=None, use_allocator: bool = True):
+    """lbks_device on torch's current stream (or `stream`), with allocations served
+    by the PyTorch caching allocator.  Returns (struct, keepalive)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    dev = lbks_device()
+    dev.stream = c_void_p(s.cuda_stream)
+    dev.device = device
+    keep = [s]
+    if use_allocator:
+        def _alloc(nbytes, user):
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, s)
+
+        def _free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+        dev.alloc, dev.free = a, f
+        keep += [a, f]
+    return dev, keep
+
+
+def params(N, h, n_orb, n_elec, **kw) -> lbks_params:
+    p = lbks_params_default()
+    if isinstance(N, int):
+        N = (N, N, N)
+    p.N[0], p.N[1], p.N[2] = N
+    p.h, p.n_orb, p.n_elec = h, n_orb, n_elec
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def params_for(system, **kw) -> lbks_params:
+    """Parameters for an inputs.System (grid, spacing, electrons, softening, start)."""
+    init = LBKS_INIT_GAUSS_NOISE if system.init == "gauss_noise" else LBKS_INIT_RANDOM_GAUSS
+    base = dict(softening=system.softening, init=init, init_sigma=system.init_sigma,
+                init_noise=system.init_noise, seed=system.seed)
+    base.update(kw)
+    return params(tuple(system.dims), system.h, system.n_orb, system.n_elec, **base)
+
+
+class Solver:
+    """One solve context on one GPU."""
+
+    def __init__(self, p: lbks_params, device: int = 0, use_torch: bool = True, stream=None):
+        self._keep = []
+        dev = None
+        if use_torch:
+            dev, self._keep = torch_device_binding(device, stream)
+        self.p = p
+        self.ctx = lbks_create(p, dev)
+        self.n_orb = p.n_orb
+
+    @classmethod
+    def for_system(cls, system, set_nuclei=True, **kw):
+        use_torch = kw.pop("use_torch", True)
+        s = cls(params_for(system, **kw), use_torch=use_torch)
+        if set_nuclei:
+            s.set_nuclei(system.Z, system.R)
+        return s
+
+    def set_nuclei(self, Z, R):
+        lbks_set_nuclei(self.ctx, Z, R)
+
+    def set_potential(self, v):
+        lbks_set_potential(self.ctx, v)
+
+    def set_orbitals(self, psi):
+        lbks_set_orbitals(self.ctx, psi)
+
+    def relax(self, max_steps, dE_tol=0.0, check_every=100):
+        return lbks_relax(self.ctx, max_steps, dE_tol, check_every)
+
+    def energy(self) -> dict:
+        return lbks_energy(self.ctx).as_dict(self.n_orb)
+
+    def orbitals(self):
+        return lbks_orbitals(self.ctx)
+
+    def device_bytes(self) -> int:
+        return load().lbks_device_bytes(self.ctx)
+
+    def set_timing(self, on: bool):
+        _check(self.ctx, load().lbks_set_timing(self.ctx, 1 if on else 0))
+
+    def kernel_time(self):
+        ms = c_double()
+        n = c_int64()
+        _check(self.ctx, load().lbks_kernel_time(self.ctx, 0, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if self.ctx:
+            lbks_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on the
+same seeded inputs.
+
+Bars: FP64 total energy within 1e-10 relative and density within 1e-9 max-abs;
+FP32-bulk |dE| <= 1e-5 Ha, |d eps_j| <= 1e-5 Ha, density relative L2 <= 1e-4.
+Sizes span several 256-node tiles with a ragged tail (e.g. 20^3 = 31.25 tiles).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1507_07666_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    from paper_1507_07666_amd import lbks
+    lbks.load()
+    return lbks
+
+
+def say(*a):
+    print("[gpu]", *a, file=sys.stderr, flush=True)
+
+
+ORTHO = {0: "gs", 1: "w"}
+
+
+def make_pair(L, system, user_init=True, **kw):
+    """(GPU solver, oracle) on the same system; kw are lbks_params fields."""
+    p = L.params_for(system, **({"init": L.LBKS_INIT_USER} if user_init else {}), **kw)
+    s = L.Solver(p)
+    s.set_nuclei(system.Z, system.R)
+    if user_init:
+        s.set_orbitals(system.psi0())
+    okw = dict(omega=p.omega, D=p.D, ortho=ORTHO[p.ortho], xc=p.xc, hartree=bool(p.hartree),
+               poisson_sweeps=p.poisson_sweeps, rho_floor=p.rho_floor)
+    o = O.oracle_for(system, **okw)
+    return s, o
+
+
+def compare_state(s, o, tol_rho=1e-9, tol_psi=1e-10):
+    psi, rho = s.orbitals()
+    psi_o, rho_o = o.state()
+    n = psi.shape[0]
+    assert np.max(np.abs(rho.ravel() - rho_o)) <= tol_rho * max(1.0, np.abs(rho_o).max())
+    assert np.max(np.abs(psi.reshape(n, -1) - psi_o)) <= tol_psi * max(1.0, np.abs(psi_o).max())
+
+
+def compare_energy(e, eo, rel=1e-10):
+    assert abs(e["e_total"] - eo.e_total) <= rel * abs(eo.e_total), (e["e_total"], eo.e_total)
+    for k in ("e_kin", "e_ext", "e_hartree", "e_x", "e_c", "e_nn", "n_electrons"):
+        ref = getattr(eo, k)
+        assert abs(e[k] - ref) <= rel * max(1.0, abs(ref)), (k, e[k], ref)
+    n = len(eo.eps)
+    assert np.allclose(e["eps"][:n], eo.eps, rtol=0, atol=rel * max(1.0, np.abs(eo.eps).max()))
+
+
+@pytest.mark.parametrize("case", ["he16", "ne20"])
+def test_single_steps_fp64(L, case):
+    system = I.he_atom().scaled(16) if case == "he16" else I.ne_atom().scaled(20)
+    say("single steps", case)
+    s, o = make_pair(L, system)
+    compare_state(s, o, 1e-13, 1e-13)
+    for k in (1, 2):
+        s.relax(k)
+        for _ in range(k):
+            o.step()
+        compare_state(s, o, 1e-12, 1e-12)
+    compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-11)
+    s.close()
+
+
+@pytest.mark.parametrize("variant", ["gs", "w", "omega0.8", "omega1.3", "pz81", "x_only",
+                                     "no_hartree", "sweeps0", "d0.3"])
+def test_relaxation_variants_fp64(L, variant):
+    system = I.ne_atom().scaled(20)
+    kw = {"gs": {}, "w": dict(ortho=L.LBKS_ORTHO_W), "omega0.8": dict(omega=0.8),
+          "omega1.3": dict(omega=1.3), "pz81": dict(xc=L.LBKS_XC_X_PZ81), "x_only": dict(xc=L.LBKS_XC_X),
+          "no_hartree": dict(hartree=0), "sweeps0": dict(poisson_sweeps=0),
+          "d0.3": dict(D=0.3)}[variant]
+    say("variant", variant)
+    s, o = make_pair(L, system, **kw)
+    s.relax(40)
+    for _ in range(40):
+        o.step()
+    compare_state(s, o, 1e-10, 1e-10)
+    compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
+def test_collapsed_scheme_matches_population_oracle(L):
+    system = I.ne_atom().scaled(20)
+    say("collapsed scheme")
+    s, o = make_pair(L, system, scheme=L.LBKS_SCHEME_COLLAPSED)
+    s.relax(40)
+    for _ in range(40):
+        o.step()
+    compare_state(s, o, 1e-10, 1e-10)
+    compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
+def test_device_initial_orbitals_match_seeded_generator(L):
+    """SplitMix64 start generated on the device equals the inputs module's."""
+    for system in (I.he_atom().scaled(12), I.ne_atom().scaled(12)):
+        say("device init", system.name)
+        s, o = make_pair(L, system, user_init=False)
+        compare_state(s, o, 1e-13, 1e-13)
+        s.close()
+
+
+def test_he_workload_2000_steps_fp64(L):
+    """He, 32^3 at 0.3 bohr, softening 0.1, Gaussian + 1e-3 noise (seed 1), exactly 2000
+    steps; device-generated start."""
+    system = I.he_atom()
+    say("He 2000 steps fp64")
+    s, o = make_pair(L, system, user_init=False)
+    rc, steps = s.relax(2000)
+    assert steps == 2000
+    o.relax(2000)
+    e = s.energy()
+    eo = o.energies(converge_poisson=True)
+    compare_energy(e, eo, 1e-10)
+    _, rho = s.orbitals()
+    _, rho_o = o.state()
+    assert np.max(np.abs(rho.ravel() - rho_o)) <= 1e-9
+    s.close()
+
+
+def test_he_workload_fp32_bulk_against_fp64_oracle(L):
+    system = I.he_atom()
+    say("He 2000 steps fp32")
+    s, o = make_pair(L, system, user_init=False, precision=L.LBKS_FP32_BULK)
+    s.relax(2000)
+    o.relax(2000)
+    e = s.energy()
+    eo = o.energies(converge_poisson=True)
+    assert abs(e["e_total"] - eo.e_total) <= 1e-5
+    assert abs(e["eps"][0] - eo.eps[0]) <= 1e-5
+    _, rho = s.orbitals()
+    _, rho_o = o.state()
+    assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-4 * np.linalg.norm(rho_o)
+    s.close()
+
+
+def test_convergence_control_matches_oracle(L):
+    system = I.he_atom().scaled(16, h=0.4)
+    say("relax stopping rule")
+    s, o = make_pair(L, system)
+    rc, steps = s.relax(5000, dE_tol=1e-9, check_every=25)
+    rco, steps_o = o.relax(5000, dE_tol=1e-9, check_every=25)
+    assert (rc, steps) == (rco, steps_o) and rc == 0
+    rc, steps = s.relax(37, dE_tol=0.0, check_every=10)
+    assert (rc, steps) == (L.LBKS_NOT_CONVERGED, 37)
+    s.close()
+
+
+def test_error_paths(L):
+    system = I.he_atom().scaled(12)
+    say("error paths")
+    p = L.params_for(system)
+    s = L.Solver(p)
+    with pytest.raises(L.LbksError) as ei:
+        s.relax(1)
+    assert ei.value.code == L.LBKS_E_STATE
+    with pytest.raises(L.LbksError) as ei:
+        s.set_nuclei([2.0], [[100.0, 0.0, 0.0]])
+    assert ei.value.code == L.LBKS_E_INVAL
+    with pytest.raises(L.LbksError) as ei:
+        s.set_nuclei([-1.0], [[0.0, 0.0, 0.0]])
+    assert ei.value.code == L.LBKS_E_INVAL
+    s.set_nuclei(system.Z, system.R)
+    bad = system.psi0()
+    bad[0, 3, 3, 3] = np.nan
+    s.set_orbitals(bad)          # the overlap becomes NaN: detected at the next chunk boundary
+    with pytest.raises(L.LbksError) as ei:
+        s.relax(3, dE_tol=1e-6, check_every=1)
+    assert ei.value.code == L.LBKS_E_NUMERIC
+    s.set_orbitals(system.psi0())  # recovers from a checkpoint of orbitals
+    rc, _ = s.relax(5)
+    assert rc == L.LBKS_NOT_CONVERGED
+    e = s.energy()
+    assert np.isfinite(e["e_total"])
+    s.close()
+
+
+def test_repeatable_bitwise(L):
+    system = I.ne_atom().scaled(20)
+    say("repeatability")
+    out = []
+    for _ in range(2):
+        s, _o = make_pair(L, system)
+        s.relax(15)
+        out.append(s.orbitals())
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_full_size_ne_fp64_two_steps(L):
+    """Ne at its full 96^3 size: two lattice steps, every node compared."""
+    system = I.ne_atom()
+    say("Ne 96^3 two steps")
+    s, o = make_pair(L, system)
+    s.relax(2)
+    o.step()
+    o.step()
+    compare_state(s, o, 1e-11, 1e-11)
+    s.close()
