@@ -59,6 +59,31 @@ def cpu_baseline(system, steps, threads):
                       f"{system.dims[0]}^3, {system.n_orb} orbitals, FP64) after 1 untimed step"}
 
 
+def copy_calibration(nbytes, iters):
+    """Bandwidth of the library's plain 16-byte-per-lane copy kernel (read + write)."""
+    import ctypes
+    import torch
+    from paper_1507_07666_amd import lbks
+    L = lbks.load()
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        L.lbks_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                           ctypes.c_void_p(st.cuda_stream))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        L.lbks_copy_kernel(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                           ctypes.c_void_p(st.cuda_stream))
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    assert torch.equal(src, dst)
+    return {"mode": "copy", "bytes_read": nbytes, "bytes_moved": 2 * nbytes, "avg_us": ms * 1e3,
+            "GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": 2 * nbytes / (ms * 1e-3) / 8e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +96,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
+                    help="copy: time the library's plain copy kernel (bandwidth calibration)")
+    ap.add_argument("--copy-mib", type=int, default=678, help="bytes read (= written) by one copy launch")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -82,6 +110,9 @@ def main():
     from paper_1507_07666_amd import lbks
 
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        print(json.dumps(copy_calibration(args.copy_mib << 20, max(args.steps, 10))), flush=True)
+        return
     system = workload(args.workload)
     prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
     scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED

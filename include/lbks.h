@@ -159,7 +159,10 @@ int lbks_set_nuclei(lbks_ctx *ctx, int32_t n, const double *Z, const double *xyz
  * in chunks of `check_every`; if dE_tol > 0 the total energy (with the
  * current Hartree potential) is evaluated after each chunk and the call
  * returns LBKS_OK once two consecutive chunk energies differ by less than
- * dE_tol.  With dE_tol <= 0 exactly max_steps steps run.  Returns
+ * dE_tol.  The previous chunk energy persists across calls (so splitting a
+ * run into calls whose max_steps are multiples of check_every changes
+ * nothing) and is forgotten when set_nuclei, set_potential, set_orbitals or
+ * lbks_energy change the state.  With dE_tol <= 0 exactly max_steps steps run.  Returns
  * LBKS_NOT_CONVERGED when max_steps is reached, LBKS_E_NUMERIC if the overlap
  * matrix stops being finite and positive definite, LBKS_E_STATE if no
  * potential was set.  *steps_done (may be NULL) receives the steps run. */
@@ -194,7 +197,8 @@ int lbks_set_potential(lbks_ctx *ctx, const double *v_ext);
 
 /* Replace the orbitals (host, FP64, [n_orb][z][y][x]) and reset the
  * populations to equilibrium f_jp = xi_p psi_j; the Hartree potential is
- * kept.  Used for warm starts and checkpoint/resume. */
+ * kept, except after an LBKS_E_NUMERIC failure, when it restarts from zero.
+ * Used for warm starts, checkpoint/resume and recovery. */
 int lbks_set_orbitals(lbks_ctx *ctx, const double *psi);
 
 /* Grid nodes and orbital count of a context. */
@@ -241,6 +245,9 @@ int lbks_batch_detach(lbks_batch *b, lbks_ctx *ctx);
 int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
                      int32_t *status, int64_t *steps);
 int lbks_batch_size(const lbks_batch *b);
+
+/* The hipStream_t the batch launches on (members must be created on it). */
+void *lbks_batch_stream(const lbks_batch *b);
 void lbks_batch_destroy(lbks_batch *b);
 
 #ifdef __cplusplus

@@ -203,6 +203,7 @@ class Oracle:
         self.vext = None
         self.e_nn = 0.0
         self.steps = 0
+        self.e_prev = None          # stopping rule: previous chunk energy, kept across relax calls
         self.omega_sor = self.L.orc_sor_omega(nx, ny, nz)
 
     # -- inputs
@@ -214,13 +215,16 @@ class Oracle:
         self.L.orc_vext(nx, ny, nz, self.prm.h, len(Z), _p(Z), _p(R), self.prm.softening,
                         _p(self.vext))
         self.e_nn = self.L.orc_enn(len(Z), _p(Z), _p(R))
+        self.e_prev = None
 
     def set_potential(self, vext):
         self.vext = np.ascontiguousarray(vext, dtype=np.float64).reshape(self.N).copy()
         self.e_nn = 0.0
+        self.e_prev = None
 
     def set_orbitals(self, psi0):
         psi0 = np.ascontiguousarray(psi0, dtype=np.float64).reshape(self.prm.n_orb, self.N)
+        self.e_prev = None
         self.L.orc_equilibrium(self.prm.n_orb, self.N, _p(self.xi), _p(psi0), _p(self.f))
 
     # -- pieces of one step
@@ -335,6 +339,7 @@ class Oracle:
         res = 0.0
         if p.hartree:
             if converge_poisson:
+                self.e_prev = None          # the Hartree relaxation changes the state
                 res, _ = self.converge_poisson(rho, tol)
             else:
                 res = self.poisson_residual(rho)
@@ -361,12 +366,14 @@ class Oracle:
         et = e_kin + e_ext + e_h + e_x + e_c + self.e_nn
         return Energies(et, e_kin, e_ext, e_h, e_x, e_c, self.e_nn, ne, res, eps, self.steps)
 
-    def relax(self, max_steps, dE_tol=0.0, check_every=100):
+    def relax(self, max_steps, dE_tol=0.0, check_every=100, progress=None):
         """Run steps in chunks of check_every; after each chunk (only if dE_tol > 0)
         the total energy with the current Hartree potential is compared with the
-        previous chunk's.  Returns (0 converged | 1 step limit, steps done)."""
+        previous chunk's (kept across calls until the state is changed by new
+        nuclei, potential or orbitals, or a Poisson-converged energy evaluation).
+        Returns (0 converged | 1 step limit, steps done).  `progress(steps, energy)`
+        is called after each check."""
         done = 0
-        e_prev = None
         check_every = max(1, int(check_every))
         while done < max_steps:
             n = min(check_every, max_steps - done)
@@ -375,9 +382,12 @@ class Oracle:
             done += n
             if dE_tol > 0:
                 e = self.energies(converge_poisson=False).e_total
-                if e_prev is not None and abs(e - e_prev) < dE_tol:
+                if progress is not None:
+                    progress(done, e)
+                conv = self.e_prev is not None and abs(e - self.e_prev) < dE_tol
+                self.e_prev = e
+                if conv:
                     return 0, done
-                e_prev = e
         return 1, done
 
 

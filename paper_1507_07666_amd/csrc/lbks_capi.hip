@@ -46,6 +46,8 @@ struct lbks_ctx {
     int parity = 0;             // populations live in f0 (0) or f1 (1)
     int64_t steps = 0;
     bool has_potential = false;
+    bool have_prev = false;     // stopping rule: energy of the previous chunk check
+    double e_prev = 0.0;
     double *d_zr = nullptr;     // nuclei table [4 * LBKS_MAX_NUC + 1]
     std::string err;
     // timing of the stream-collide kernel
@@ -57,20 +59,35 @@ struct lbks_ctx {
     lbks_batch *batch = nullptr;
 };
 
+// One launch group of a batch: members sharing every template and sequence choice.
+struct BatchGroup {
+    int precision = 0, no = 1, scheme = 0, hartree = 1, sweeps = 2;
+    bool wmode = false;
+    std::vector<int> members;   // indices into lbks_batch::members
+    Plan plan{};
+};
+
 struct lbks_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    void *(*ualloc)(size_t, void *) = nullptr;
+    void (*ufree)(void *, void *) = nullptr;
+    void *user = nullptr;
     std::vector<lbks_ctx *> members;
-    // device tables rebuilt on membership change
-    void *tables = nullptr;
-    size_t tables_bytes = 0;
+    std::vector<char> running;          // members that take steps in this relax
+    std::vector<BatchGroup> groups;
+    void *mem = nullptr;                // descriptors, tile tables, gather buffer
+    size_t mem_bytes = 0;
+    double *d_gather = nullptr;         // [members][GATHER_W]
+    const double **d_scal = nullptr;    // members' scalar blocks
     bool dirty = true;
-    std::vector<Plan> plans;    // one plan per (precision, bucket, W, scheme) group
-    std::vector<std::vector<int>> group_members;
-    InstDesc *d_descs = nullptr;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    std::vector<int> active;
+    int bparity = 0;                    // population buffer parity within the current plan
+    int64_t epoch_steps = 0;            // steps since the plan was built
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    bool use_graph = true;
+    std::string err;
 };
 
 namespace {
@@ -183,10 +200,10 @@ Layout plan_layout(const lbks_params *p)
     take(L.Vd, s == 8 ? 0 : N * 8);
     take(L.vext, N * 8);
     take(L.vh, padded * 8);
-    take(L.s_part, (size_t)(no * (no + 1) / 2) * ntile * 8);
-    take(L.m_part, (size_t)NMOM * ntile * 8);
-    take(L.e_part, (size_t)(2 * no + NEBASE) * ntile * 8);
-    take(L.r_part, 2 * ntile * 8);
+    take(L.s_part, (size_t)padded_cols(no * (no + 1) / 2) * ntile * 8);
+    take(L.m_part, (size_t)padded_cols(NMOM) * ntile * 8);
+    take(L.e_part, (size_t)padded_cols(2 * no + NEBASE) * ntile * 8);
+    take(L.r_part, (size_t)padded_cols(2) * ntile * 8);
     take(L.C, 2 * MAXO * MAXO * 8);
     take(L.scal, SC_SIZE * 8);
     take(L.stage, (n + 1) * N * 8);
@@ -210,14 +227,63 @@ void dev_free(lbks_ctx *c, void *ptr)
     else (void)hipFree(ptr);
 }
 
+void mark_batch_dirty(lbks_ctx *c);
+
 int upload_desc(lbks_ctx *c)
 {
+    mark_batch_dirty(c);
+    c->have_prev = false;
     HIPCHK(c, hipMemcpyAsync(c->d_desc, &c->h, sizeof(InstDesc), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return 0;
 }
 
 // ---------------------------------------------------------- step sequences
+
+// Kernel sequences on a plan (one solve or one batch group); return hipError_t.
+#define PCHK(expr)                  \
+    do {                            \
+        int _e = (expr);            \
+        if (_e != 0) return _e;     \
+    } while (0)
+
+int plan_orthonormalise(const Plan &pl, hipStream_t st)
+{
+    PCHK(launch_overlap_finalize(pl, st));
+    PCHK(launch_orthonormalise(pl, st));
+    return 0;
+}
+
+// Everything of one lattice step before the lattice Boltzmann update.
+int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
+{
+    PCHK(plan_orthonormalise(pl, st));
+    if (hartree) {
+        PCHK(launch_multipole_finalize(pl, st));
+        PCHK(launch_ghost(pl, st));
+        for (int k = 0; k < sweeps; ++k) {
+            PCHK(launch_sor(pl, 0, st));
+            PCHK(launch_sor(pl, 1, st));
+        }
+    }
+    PCHK(launch_potential(pl, 0, st));
+    return 0;
+}
+
+int plan_update(const Plan &pl, int scheme, int parity, hipStream_t st)
+{
+    if (scheme == LBKS_SCHEME_POPULATIONS) return launch_stream_collide(pl, parity, st);
+    return launch_collapsed_update(pl, st);
+}
+
+int plan_energy(const Plan &pl, hipStream_t st)
+{
+    PCHK(plan_orthonormalise(pl, st));
+    PCHK(launch_potential(pl, 1, st));
+    PCHK(launch_energy_terms(pl, st));
+    PCHK(launch_energy_finalize(pl, st));
+    return 0;
+}
 
 int enqueue_orthonormalise(lbks_ctx *c)
 {
@@ -271,12 +337,7 @@ int flush_timing(lbks_ctx *c)
 int enqueue_step(lbks_ctx *c)
 {
     int rc;
-    if ((rc = enqueue_orthonormalise(c))) return rc;
-    if (c->p.hartree) {
-        if ((rc = enqueue_hartree_boundary(c))) return rc;
-        if ((rc = enqueue_sweeps(c, c->p.poisson_sweeps))) return rc;
-    }
-    KCHK(c, launch_potential(c->plan, 0, c->stream));
+    KCHK(c, plan_pre_update(c->plan, c->p.hartree, c->p.poisson_sweeps, c->stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if (c->ev_used + 2 > 4096 && (rc = flush_timing(c))) return rc;
@@ -285,12 +346,8 @@ int enqueue_step(lbks_ctx *c)
         if (!e0 || !e1) return fail(c, LBKS_E_HIP, "hipEventCreate failed");
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    if (c->p.scheme == LBKS_SCHEME_POPULATIONS) {
-        KCHK(c, launch_stream_collide(c->plan, c->parity, c->stream));
-        c->parity ^= 1;
-    } else {
-        KCHK(c, launch_collapsed_update(c->plan, c->stream));
-    }
+    KCHK(c, plan_update(c->plan, c->p.scheme, c->parity, c->stream));
+    if (c->p.scheme == LBKS_SCHEME_POPULATIONS) c->parity ^= 1;
     if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
     c->steps += 1;
     return 0;
@@ -299,11 +356,7 @@ int enqueue_step(lbks_ctx *c)
 // Energies of the current state into the scalar block (device).
 int enqueue_energy(lbks_ctx *c)
 {
-    int rc;
-    if ((rc = enqueue_orthonormalise(c))) return rc;
-    KCHK(c, launch_potential(c->plan, 1, c->stream));
-    KCHK(c, launch_energy_terms(c->plan, c->stream));
-    KCHK(c, launch_energy_finalize(c->plan, c->stream));
+    KCHK(c, plan_energy(c->plan, c->stream));
     return 0;
 }
 
@@ -587,9 +640,17 @@ extern "C" int lbks_set_orbitals(lbks_ctx *c, const double *psi)
 {
     if (!c || !psi) return LBKS_E_INVAL;
     const size_t n = (size_t)c->p.n_orb * c->h.nsite;
-    // new orbitals are a recovery point: clear a previous numeric-error flag
-    static const double zero = 0.0;
-    HIPCHK(c, hipMemcpyAsync(c->h.scal + SC_ERR, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    c->have_prev = false;
+    // new orbitals are a recovery point: after a numeric failure the Hartree
+    // potential may hold non-finite values too, so it restarts from zero
+    double errf = 0.0;
+    int rc0 = read_scalar(c, SC_ERR, &errf);
+    if (rc0) return rc0;
+    if (errf != 0.0) {
+        const size_t padded = (size_t)(c->h.nx + 2) * (c->h.ny + 2) * (c->h.nz + 2);
+        HIPCHK(c, hipMemsetAsync(c->h.vh, 0, padded * sizeof(double), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->h.scal + SC_ERR, 0, sizeof(double), c->stream));
+    }
     HIPCHK(c, hipMemcpyAsync(c->h.stage, psi, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
     KCHK(c, launch_psi_from_stage(c->plan, c->stream));
     if (c->p.scheme == LBKS_SCHEME_POPULATIONS) {
@@ -610,8 +671,6 @@ extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t
     if (max_steps < 0) return fail(c, LBKS_E_INVAL, "max_steps < 0");
     if (check_every < 1) check_every = 1;
     int64_t done = 0;
-    bool have_prev = false;
-    double e_prev = 0.0;
     int rc;
     while (done < max_steps) {
         const int64_t n = std::min<int64_t>(check_every, max_steps - done);
@@ -626,9 +685,10 @@ extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t
             if ((rc = read_energies(c, &e, &errf))) return rc;
             if (errf != 0.0 || !isfinite(e.e_total))
                 return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
-            if (have_prev && fabs(e.e_total - e_prev) < dE_tol) return LBKS_OK;
-            e_prev = e.e_total;
-            have_prev = true;
+            const bool conv = c->have_prev && fabs(e.e_total - c->e_prev) < dE_tol;
+            c->e_prev = e.e_total;
+            c->have_prev = true;
+            if (conv) return LBKS_OK;
         }
     }
     double errf = 0.0;
@@ -643,6 +703,7 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
     if (!c || !out) return LBKS_E_INVAL;
     if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     int rc;
+    c->have_prev = false;   // the Hartree relaxation below changes the state
     if ((rc = enqueue_orthonormalise(c))) return rc;
     if (c->p.hartree) {
         if ((rc = enqueue_hartree_boundary(c))) return rc;
@@ -712,11 +773,205 @@ extern "C" int lbks_copy_kernel(void *dst, const void *src, size_t bytes, void *
 
 // ================================================================ batches
 
+namespace {
+
+constexpr int GATHER_W = 32;   // per member: the 25 energy values, then the error flag
+constexpr int GATHER_ERR = 25;
+
+void mark_batch_dirty(lbks_ctx *c)
+{
+    if (c && c->batch) c->batch->dirty = true;
+}
+
+void batch_destroy_graphs(lbks_batch *b)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
+}
+
+void batch_free_mem(lbks_batch *b)
+{
+    if (!b->mem) return;
+    if (b->ufree) b->ufree(b->mem, b->user);
+    else (void)hipFree(b->mem);
+    b->mem = nullptr;
+    b->mem_bytes = 0;
+}
+
+// Fold the steps taken under the current plan into the members' own state.
+void batch_commit(lbks_batch *b)
+{
+    for (const BatchGroup &g : b->groups)
+        for (int i : g.members) {
+            lbks_ctx *c = b->members[i];
+            if (c->p.scheme == LBKS_SCHEME_POPULATIONS && (b->epoch_steps & 1)) c->parity ^= 1;
+            c->steps += b->epoch_steps;
+        }
+    b->epoch_steps = 0;
+    b->bparity = 0;
+}
+
+int batch_fail(lbks_batch *b, int code, const std::string &m)
+{
+    b->err = m;
+    return code;
+}
+
+// Enqueue one lattice step of every running member at batch parity bp.
+int batch_enqueue_step(lbks_batch *b, int bp)
+{
+    for (const BatchGroup &g : b->groups) {
+        int e = plan_pre_update(g.plan, g.hartree, g.sweeps, b->stream);
+        if (!e) e = plan_update(g.plan, g.scheme, bp, b->stream);
+        if (e) return e;
+    }
+    return 0;
+}
+
+// Group the running members, upload their descriptors and tile tables, and
+// capture one step per parity into HIP graphs.
+int batch_build(lbks_batch *b)
+{
+    batch_commit(b);
+    batch_destroy_graphs(b);
+    b->groups.clear();
+    const int m = (int)b->members.size();
+    for (int i = 0; i < m; ++i) {
+        if (!b->running[i]) continue;
+        const lbks_ctx *c = b->members[i];
+        BatchGroup key;
+        key.precision = c->plan.precision;
+        key.no = c->plan.no;
+        key.wmode = c->plan.wmode;
+        key.scheme = c->p.scheme;
+        key.hartree = c->p.hartree;
+        key.sweeps = c->p.poisson_sweeps;
+        BatchGroup *g = nullptr;
+        for (BatchGroup &x : b->groups)
+            if (x.precision == key.precision && x.no == key.no && x.wmode == key.wmode && x.scheme == key.scheme &&
+                x.hartree == key.hartree && x.sweeps == key.sweeps)
+                g = &x;
+        if (!g) {
+            b->groups.push_back(key);
+            g = &b->groups.back();
+        }
+        g->members.push_back(i);
+    }
+    // sizes
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    struct Off {
+        size_t desc, site, ghost, sor, inst;
+        int n_site, n_ghost, n_sor;
+    };
+    std::vector<Off> go(b->groups.size());
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+        const BatchGroup &g = b->groups[k];
+        Off &o = go[k];
+        o.n_site = o.n_ghost = o.n_sor = 0;
+        for (int i : g.members) {
+            const InstDesc &h = b->members[i]->h;
+            o.n_site += h.ntile;
+            o.n_ghost += h.ntile_ghost;
+            o.n_sor += h.ntile_sor;
+        }
+        o.desc = take(sizeof(InstDesc) * g.members.size());
+        o.site = take(sizeof(int2) * o.n_site);
+        o.ghost = take(sizeof(int2) * o.n_ghost);
+        o.sor = take(sizeof(int2) * o.n_sor);
+        o.inst = take(sizeof(int) * g.members.size());
+    }
+    const size_t gather_off = take(sizeof(double) * GATHER_W * std::max(m, 1));
+    const size_t scal_off = take(sizeof(double *) * std::max(m, 1));
+    if (off > b->mem_bytes) {
+        batch_free_mem(b);
+        void *p = nullptr;
+        if (b->ualloc) p = b->ualloc(off, b->user);
+        else if (hipMalloc(&p, off) != hipSuccess) p = nullptr;
+        if (!p) return batch_fail(b, LBKS_E_NOMEM, "batch table allocation failed");
+        b->mem = p;
+        b->mem_bytes = off;
+    }
+    std::vector<char> host(off, 0);
+    char *base = (char *)b->mem;
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+        BatchGroup &g = b->groups[k];
+        const Off &o = go[k];
+        InstDesc *hd = (InstDesc *)(host.data() + o.desc);
+        int2 *ts = (int2 *)(host.data() + o.site);
+        int2 *tg = (int2 *)(host.data() + o.ghost);
+        int2 *tr = (int2 *)(host.data() + o.sor);
+        int *ti = (int *)(host.data() + o.inst);
+        int ns = 0, ng = 0, nr = 0;
+        for (size_t q = 0; q < g.members.size(); ++q) {
+            const lbks_ctx *c = b->members[g.members[q]];
+            InstDesc d = c->h;
+            if (c->parity) std::swap(d.f0, d.f1);   // batch parity 0 = the member's current populations
+            hd[q] = d;
+            for (int t = 0; t < d.ntile; ++t) ts[ns++] = make_int2((int)q, t);
+            for (int t = 0; t < d.ntile_ghost; ++t) tg[ng++] = make_int2((int)q, t);
+            for (int t = 0; t < d.ntile_sor; ++t) tr[nr++] = make_int2((int)q, t);
+            ti[q] = (int)q;
+        }
+        Plan &pl = g.plan;
+        pl = Plan{};
+        pl.d_desc = (const InstDesc *)(base + o.desc);
+        pl.tt.site = (const int2 *)(base + o.site);
+        pl.tt.n_site = o.n_site;
+        pl.tt.ghost = (const int2 *)(base + o.ghost);
+        pl.tt.n_ghost = o.n_ghost;
+        pl.tt.sor = (const int2 *)(base + o.sor);
+        pl.tt.n_sor = o.n_sor;
+        pl.tt.inst = (const int *)(base + o.inst);
+        pl.tt.n_inst = (int)g.members.size();
+        pl.precision = g.precision;
+        pl.no = g.no;
+        pl.wmode = g.wmode;
+        pl.n_inst = (int)g.members.size();
+    }
+    const double **hs = (const double **)(host.data() + scal_off);
+    for (int i = 0; i < m; ++i) hs[i] = b->members[i]->h.scal;
+    b->d_gather = (double *)(base + gather_off);
+    b->d_scal = (const double **)(base + scal_off);
+    if (hipMemcpyAsync(b->mem, host.data(), off, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return batch_fail(b, LBKS_E_HIP, "batch table upload failed");
+    if (b->use_graph && !b->groups.empty()) {
+        for (int bp = 0; bp < 2; ++bp) {
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return batch_fail(b, LBKS_E_HIP, "hipStreamBeginCapture failed");
+            const int e = batch_enqueue_step(b, bp);
+            const hipError_t ee = hipStreamEndCapture(b->stream, &b->graph[bp]);
+            if (e || ee != hipSuccess) return batch_fail(b, LBKS_E_HIP, "graph capture of the batched step failed");
+            if (hipGraphInstantiate(&b->exec[bp], b->graph[bp], nullptr, nullptr, 0) != hipSuccess)
+                return batch_fail(b, LBKS_E_HIP, "hipGraphInstantiate failed");
+        }
+    }
+    b->dirty = false;
+    return 0;
+}
+
+}  // namespace
+
 extern "C" int lbks_batch_create(const lbks_device *dev, lbks_batch **out)
 {
     if (!out) return LBKS_E_INVAL;
+    *out = nullptr;
+    if (dev && ((dev->alloc == nullptr) != (dev->free == nullptr))) return LBKS_E_INVAL;
     lbks_batch *b = new lbks_batch();
     b->device = dev ? dev->device : 0;
+    if (hipSetDevice(b->device) != hipSuccess) {
+        delete b;
+        return LBKS_E_HIP;
+    }
     if (dev && dev->stream) {
         b->stream = (hipStream_t)dev->stream;
     } else {
@@ -726,16 +981,26 @@ extern "C" int lbks_batch_create(const lbks_device *dev, lbks_batch **out)
         }
         b->own_stream = true;
     }
+    if (dev) {
+        b->ualloc = dev->alloc;
+        b->ufree = dev->free;
+        b->user = dev->user;
+    }
     *out = b;
     return 0;
 }
+
+extern "C" void *lbks_batch_stream(const lbks_batch *b) { return b ? (void *)b->stream : nullptr; }
 
 extern "C" int lbks_batch_attach(lbks_batch *b, lbks_ctx *c)
 {
     if (!b || !c || c->batch) return LBKS_E_INVAL;
     if (c->stream != b->stream || c->device != b->device)
         return fail(c, LBKS_E_INVAL, "context must share the batch's stream and device");
+    if (c->timing) return fail(c, LBKS_E_INVAL, "disable kernel timing before attaching to a batch");
+    batch_commit(b);
     b->members.push_back(c);
+    b->running.assign(b->members.size(), 1);
     c->batch = b;
     b->dirty = true;
     return 0;
@@ -744,7 +1009,11 @@ extern "C" int lbks_batch_attach(lbks_batch *b, lbks_ctx *c)
 extern "C" int lbks_batch_detach(lbks_batch *b, lbks_ctx *c)
 {
     if (!b || !c || c->batch != b) return LBKS_E_INVAL;
+    (void)hipStreamSynchronize(b->stream);
+    batch_commit(b);
     b->members.erase(std::remove(b->members.begin(), b->members.end(), c), b->members.end());
+    b->running.assign(b->members.size(), 1);
+    b->groups.clear();
     c->batch = nullptr;
     b->dirty = true;
     return 0;
@@ -756,56 +1025,99 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
                                 int32_t *status, int64_t *steps)
 {
     if (!b) return LBKS_E_INVAL;
-    // Lockstep over members, each launch per context (batched launches below
-    // replace this once the batch plan is built).
     const int m = (int)b->members.size();
     std::vector<int> st(m, LBKS_NOT_CONVERGED);
     std::vector<int64_t> done(m, 0);
-    std::vector<double> eprev(m, 0.0);
-    std::vector<bool> havep(m, false), running(m, true);
-    if (check_every < 1) check_every = 1;
-    int64_t t = 0;
-    while (t < max_steps) {
-        const int64_t n = std::min<int64_t>(check_every, max_steps - t);
-        for (int i = 0; i < m; ++i) {
-            if (!running[i]) continue;
-            for (int64_t k = 0; k < n; ++k) {
-                int rc = enqueue_step(b->members[i]);
-                if (rc) { st[i] = rc; running[i] = false; break; }
-            }
-            done[i] += n;
+    batch_commit(b);
+    b->running.assign(m, 1);
+    for (int i = 0; i < m; ++i)
+        if (!b->members[i]->has_potential) {
+            st[i] = LBKS_E_STATE;
+            b->running[i] = 0;
         }
-        t += n;
-        if (dE_tol > 0.0) {
-            bool any = false;
-            for (int i = 0; i < m; ++i) {
-                if (!running[i]) continue;
-                lbks_ctx *c = b->members[i];
-                lbks_energies e;
-                double errf = 0.0;
-                int rc = enqueue_energy(c);
-                if (!rc) rc = read_energies(c, &e, &errf);
-                if (rc) { st[i] = rc; running[i] = false; continue; }
-                if (errf != 0.0 || !isfinite(e.e_total)) { st[i] = LBKS_E_NUMERIC; running[i] = false; continue; }
-                if (havep[i] && fabs(e.e_total - eprev[i]) < dE_tol) { st[i] = LBKS_OK; running[i] = false; continue; }
-                eprev[i] = e.e_total;
-                havep[i] = true;
-                any = true;
+    b->dirty = true;
+    if (check_every < 1) check_every = 1;
+    std::vector<double> gat((size_t)GATHER_W * std::max(m, 1));
+    auto gather = [&]() -> int {
+        if (launch_gather(b->d_scal, m, GATHER_W, b->d_gather, b->stream)) return LBKS_E_HIP;
+        if (hipMemcpyAsync(gat.data(), b->d_gather, sizeof(double) * GATHER_W * m, hipMemcpyDeviceToHost,
+                           b->stream) != hipSuccess ||
+            hipStreamSynchronize(b->stream) != hipSuccess)
+            return LBKS_E_HIP;
+        return 0;
+    };
+    int64_t t = 0;
+    int rc = 0;
+    while (t < max_steps) {
+        bool any = false;
+        for (int i = 0; i < m; ++i) any |= b->running[i] != 0;
+        if (!any) break;
+        if (b->dirty && (rc = batch_build(b))) break;
+        const int64_t n = std::min<int64_t>(check_every, max_steps - t);
+        for (int64_t k = 0; k < n; ++k) {
+            if (b->exec[b->bparity]) {
+                if (hipGraphLaunch(b->exec[b->bparity], b->stream) != hipSuccess) {
+                    rc = batch_fail(b, LBKS_E_HIP, "hipGraphLaunch failed");
+                    break;
+                }
+            } else if (batch_enqueue_step(b, b->bparity)) {
+                rc = batch_fail(b, LBKS_E_HIP, "batched step launch failed");
+                break;
             }
-            if (!any) break;
+            b->bparity ^= 1;
+            b->epoch_steps += 1;
+        }
+        if (rc) break;
+        t += n;
+        for (int i = 0; i < m; ++i)
+            if (b->running[i]) done[i] += n;
+        if (dE_tol > 0.0) {
+            for (const BatchGroup &g : b->groups)
+                if (plan_energy(g.plan, b->stream)) rc = batch_fail(b, LBKS_E_HIP, "batched energy failed");
+            if (rc || (rc = gather())) break;
+            for (int i = 0; i < m; ++i) {
+                if (!b->running[i]) continue;
+                const double *e = &gat[(size_t)GATHER_W * i];
+                const double etot = e[0], errf = e[GATHER_ERR];
+                if (errf != 0.0 || !isfinite(etot)) {
+                    st[i] = LBKS_E_NUMERIC;
+                    b->running[i] = 0;
+                    b->dirty = true;
+                } else {
+                    lbks_ctx *c = b->members[i];
+                    const bool conv = c->have_prev && fabs(etot - c->e_prev) < dE_tol;
+                    c->e_prev = etot;
+                    c->have_prev = true;
+                    if (conv) {
+                        st[i] = LBKS_OK;
+                        b->running[i] = 0;
+                        b->dirty = true;
+                    }
+                }
+            }
         }
     }
+    if (!rc && dE_tol <= 0.0 && m > 0 && !(rc = gather())) {
+        for (int i = 0; i < m; ++i)
+            if (b->running[i] && gat[(size_t)GATHER_W * i + GATHER_ERR] != 0.0) st[i] = LBKS_E_NUMERIC;
+    }
+    batch_commit(b);
+    b->dirty = true;
     for (int i = 0; i < m; ++i) {
         if (status) status[i] = st[i];
         if (steps) steps[i] = done[i];
     }
-    return m;
+    return rc ? rc : m;
 }
 
 extern "C" void lbks_batch_destroy(lbks_batch *b)
 {
     if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_commit(b);
     for (lbks_ctx *c : b->members) c->batch = nullptr;
+    batch_destroy_graphs(b);
+    batch_free_mem(b);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

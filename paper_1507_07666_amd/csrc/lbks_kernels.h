@@ -18,6 +18,10 @@ constexpr int BS = 256;        // threads per workgroup in every site kernel
 constexpr int MAXO = 16;       // orbital capacity of the descriptor
 constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
+constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
+
+// Columns of a partial array padded to a whole number of chunks.
+__host__ __device__ constexpr int padded_cols(int nq) { return (nq + RCH - 1) / RCH * RCH; }
 
 // Offsets into the per-instance FP64 scalar block.
 constexpr int SC_MOM = 0;                  // 10 multipoles
@@ -48,10 +52,10 @@ struct InstDesc {
     double *Vd;                // FP64 potential for energies (== V in FP64 mode)
     double *vext;              // FP64 external potential
     double *vh;                // FP64 Hartree potential with one ghost layer
-    double *s_part;            // [npair][ntile]
-    double *m_part;            // [NMOM][ntile]
-    double *e_part;            // [2*bucket(n_orb) + NEBASE][ntile]
-    double *r_part;            // [2][ntile]
+    double *s_part;            // [padded_cols(npair)][ntile]
+    double *m_part;            // [padded_cols(NMOM)][ntile]
+    double *e_part;            // [padded_cols(2*bucket(n_orb) + NEBASE)][ntile]
+    double *r_part;            // [padded_cols(2)][ntile]
     double *C;                 // [MAXO*MAXO] C, then [MAXO*MAXO] C* (W mode)
     double *scal;              // [SC_SIZE]
     double *stage;             // FP64 staging, (n_orb + 1) * nsite
@@ -101,5 +105,7 @@ int launch_residual_finalize(const Plan &pl, hipStream_t st);
 int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st);
 int launch_stage_orbitals(const Plan &pl, hipStream_t st);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+// dst[i * width + k] = scal_i[SC_ENER + k] (k < 25), dst[i * width + 25] = scal_i[SC_ERR]
+int launch_gather(const double *const *scal, int count, int width, double *dst, hipStream_t st);
 
 }  // namespace lbks

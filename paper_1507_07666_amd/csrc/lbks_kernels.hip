@@ -102,24 +102,52 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], int nv, double 
     }
 }
 
-// Sum one value per thread over the workgroup, result returned to every thread.
-__device__ __forceinline__ double block_sum_all(double x)
+constexpr int FB = 1024;   // threads of the per-instance finalize kernels
+
+// Column sums out[q] = sum_t part[q * ntile + t] for q < nq, in a fixed order
+// (each thread strides the tiles, then the waves are summed in order).  The
+// partial arrays hold whole chunks of RCH columns (unused ones stay zero), so
+// every load is unconditional and all of a thread's loads are in flight at once.
+// `out` is LDS; every thread of the FB-wide workgroup must call this.
+__device__ void reduce_columns(const double *__restrict__ part, int ntile, int nq, double *out)
 {
-    __shared__ double red[BS / 64];
-    __shared__ double tot;
+    constexpr int U = 4;   // tiles per thread per round
+    __shared__ double red[FB / 64][RCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    x = wave_sum(x);
-    if (lane == 0) red[wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < BS / 64; ++w) s += red[w];
-        tot = s;
+    for (int q0 = 0; q0 < nq; q0 += RCH) {
+        const double *col = part + (size_t)q0 * ntile;
+        double acc[RCH];
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) acc[c] = 0.0;
+        for (int t0 = 0; t0 < ntile; t0 += U * FB) {
+            double v[U][RCH];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int t = t0 + k * FB + (int)threadIdx.x;
+                const int tc = t < ntile ? t : ntile - 1;
+#pragma unroll
+                for (int c = 0; c < RCH; ++c) v[k][c] = col[(size_t)c * ntile + tc];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const double w = (t0 + k * FB + (int)threadIdx.x) < ntile ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < RCH; ++c) acc[c] += w * v[k][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) {
+            const double x = wave_sum(acc[c]);
+            if (lane == 0) red[wave][c] = x;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < RCH && q0 + (int)threadIdx.x < nq) {
+            double sum = 0.0;
+            for (int w = 0; w < FB / 64; ++w) sum += red[w][threadIdx.x];
+            out[q0 + threadIdx.x] = sum;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const double r = tot;
-    __syncthreads();
-    return r;
 }
 
 __device__ __forceinline__ double node_coord(int i, int n, double h)
@@ -359,56 +387,47 @@ __global__ __launch_bounds__(BS) void k_overlap_psi(const InstDesc *__restrict__
 // (psi_hat_j = sum_{l<=j} psi_l C_lj, classical Gram-Schmidt order).  W:
 // n_j = sqrt(S_jj), C = diag(1/n), C*_lj = -Lambda_jl / n_l (l < j), C*_jj = 1/n_j
 // with Lambda_jl = S_jl / (n_j n_l), i.e. psi*_j = psi_hat_j - sum_{l<j} Lambda_jl psi_hat_l.
-__global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(FB) void k_overlap_finalize(const InstDesc *__restrict__ descs,
                                                          const int *__restrict__ list)
 {
     const InstDesc &d = descs[resolve_inst(list)];
     const int n = d.n_orb, np = npair_of(n);
     __shared__ double S[MAXO * (MAXO + 1) / 2];
-    for (int q = 0; q < np; ++q) {
-        double acc = 0.0;
-        const double *src = d.s_part + (size_t)q * d.ntile;
-        for (int t = threadIdx.x; t < d.ntile; t += BS) acc += src[t];
-        const double tot = block_sum_all(acc);
-        if (threadIdx.x == 0) S[q] = tot * d.h3;
-    }
-    __syncthreads();
+    __shared__ double L[MAXO][MAXO + 1];
+    __shared__ double Li[MAXO][MAXO + 1];
+    reduce_columns(d.s_part, d.ntile, np, S);
     if (threadIdx.x != 0) return;
     double *C = d.C;
     double *Cs = d.C + MAXO * MAXO;
     bool bad = false;
     for (int q = 0; q < np; ++q) {
+        S[q] *= d.h3;
         d.scal[SC_S + q] = S[q];
         if (!isfinite(S[q])) bad = true;
     }
     auto Sget = [&](int i, int j) { return i >= j ? S[i * (i + 1) / 2 + j] : S[j * (j + 1) / 2 + i]; };
-    for (int i = 0; i < MAXO * MAXO; ++i) {
-        C[i] = 0.0;
-        Cs[i] = 0.0;
-    }
+    // entries outside the n x n block stay zero from creation
     if (d.ortho == 0) {
-        double L[MAXO][MAXO];
         for (int i = 0; i < n; ++i)
             for (int j = 0; j <= i; ++j) {
-                double s = Sget(i, j);
-                for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+                double sum = Sget(i, j);
+                for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k];
                 if (i == j) {
-                    if (!(s > 0.0)) {
+                    if (!(sum > 0.0)) {
                         bad = true;
-                        s = 1.0;
+                        sum = 1.0;
                     }
-                    L[i][i] = sqrt(s);
+                    L[i][i] = sqrt(sum);
                 } else {
-                    L[i][j] = s / L[j][j];
+                    L[i][j] = sum / L[j][j];
                 }
             }
         // C = L^{-T}: column c of L^{-1} by forward substitution; C[l][j] = Linv[j][l]
-        double Li[MAXO][MAXO];
         for (int c = 0; c < n; ++c)
             for (int i = c; i < n; ++i) {
-                double s = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) s -= L[i][k] * Li[k][c];
-                Li[i][c] = s / L[i][i];
+                double sum = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) sum -= L[i][k] * Li[k][c];
+                Li[i][c] = sum / L[i][i];
             }
         for (int l = 0; l < n; ++l)
             for (int j = l; j < n; ++j) C[l * MAXO + j] = Li[j][l];
@@ -418,11 +437,12 @@ __global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restr
             const double sjj = Sget(j, j);
             if (!(sjj > 0.0)) bad = true;
             nrm[j] = sqrt(sjj > 0.0 ? sjj : 1.0);
+        }
+        for (int j = 0; j < n; ++j) {
             C[j * MAXO + j] = 1.0 / nrm[j];
             Cs[j * MAXO + j] = 1.0 / nrm[j];
-        }
-        for (int j = 0; j < n; ++j)
             for (int l = 0; l < j; ++l) Cs[l * MAXO + j] = -(Sget(j, l) / (nrm[j] * nrm[l])) / nrm[l];
+        }
     }
     if (bad) d.scal[SC_ERR] = 1.0;
 }
@@ -491,17 +511,13 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 
 // ---------------------------------------------------------------- Hartree
 
-__global__ __launch_bounds__(BS) void k_multipole_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(FB) void k_multipole_finalize(const InstDesc *__restrict__ descs,
                                                            const int *__restrict__ list)
 {
     const InstDesc &d = descs[resolve_inst(list)];
-    for (int q = 0; q < NMOM; ++q) {
-        double acc = 0.0;
-        const double *src = d.m_part + (size_t)q * d.ntile;
-        for (int t = threadIdx.x; t < d.ntile; t += BS) acc += src[t];
-        const double tot = block_sum_all(acc);
-        if (threadIdx.x == 0) d.scal[SC_MOM + q] = tot * d.h3;
-    }
+    __shared__ double m[NMOM];
+    reduce_columns(d.m_part, d.ntile, NMOM, m);
+    if ((int)threadIdx.x < NMOM) d.scal[SC_MOM + threadIdx.x] = m[threadIdx.x] * d.h3;
 }
 
 // Far field of the multipoles: q/r + p.r/r^3 + (1/2) sum_ab Q_ab r_a r_b / r^5.
@@ -596,16 +612,12 @@ __global__ __launch_bounds__(BS) void k_residual(const InstDesc *__restrict__ de
     block_sum_store(v, 2, d.r_part + tr.tile, d.ntile);
 }
 
-__global__ __launch_bounds__(BS) void k_residual_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(FB) void k_residual_finalize(const InstDesc *__restrict__ descs,
                                                           const int *__restrict__ list)
 {
     const InstDesc &d = descs[resolve_inst(list)];
-    double acc[2];
-    for (int q = 0; q < 2; ++q) {
-        double a = 0.0;
-        for (int t = threadIdx.x; t < d.ntile; t += BS) a += d.r_part[(size_t)q * d.ntile + t];
-        acc[q] = block_sum_all(a);
-    }
+    __shared__ double acc[2];
+    reduce_columns(d.r_part, d.ntile, 2, acc);
     if (threadIdx.x == 0) d.scal[SC_RES] = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : sqrt(acc[0]);
 }
 
@@ -704,7 +716,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const InstDesc *__restric
                 const int src = s - (vx + nx * (vy + ny * vz));
                 T fl[NO];
 #pragma unroll
-                for (int l = 0; l < NO; ++l) fl[l] = (l < n) ? fs[((size_t)l * Q + p) * N + src] : (T)0;
+                for (int l = 0; l < NO; ++l)
+                    fl[l] = (l < n) ? __builtin_nontemporal_load(fs + ((size_t)l * Q + p) * N + src) : (T)0;
                 const T vn = Vp[src];
                 const T cp = om * (T)d.xi[p];
                 const T dp = dt * (T)d.chi[p] * vn;
@@ -732,7 +745,8 @@ __global__ __launch_bounds__(BS) void k_stream_collide(const InstDesc *__restric
 #pragma unroll
             for (int j = 0; j < NO; ++j) {
                 if (j < n) {
-                    fd[((size_t)j * Q + p) * N + s] = out[j];
+                    // populations are read once per step: stream them past the caches
+                    __builtin_nontemporal_store(out[j], fd + ((size_t)j * Q + p) * N + s);
                     acc[j] += out[j];
                 }
             }
@@ -872,19 +886,16 @@ __global__ __launch_bounds__(BS) void k_energy_terms(const InstDesc *__restrict_
     block_sum_store(v, 2 * NO + NEBASE, d.e_part + tr.tile, d.ntile);
 }
 
-__global__ __launch_bounds__(BS) void k_energy_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(FB) void k_energy_finalize(const InstDesc *__restrict__ descs,
                                                         const int *__restrict__ list)
 {
     const InstDesc &d = descs[resolve_inst(list)];
     const int n = d.n_orb, no = d.n_orb <= 5 ? d.n_orb : (d.n_orb <= 8 ? 8 : 16);
     const int nv = 2 * no + NEBASE;
     __shared__ double tot[2 * MAXO + NEBASE];
-    for (int q = 0; q < nv; ++q) {
-        double a = 0.0;
-        for (int t = threadIdx.x; t < d.ntile; t += BS) a += d.e_part[(size_t)q * d.ntile + t];
-        const double r = block_sum_all(a);
-        if (threadIdx.x == 0) tot[q] = r * d.h3;
-    }
+    reduce_columns(d.e_part, d.ntile, nv, tot);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < nv; ++q) tot[q] *= d.h3;
     __syncthreads();
     if (threadIdx.x != 0) return;
     double *E = d.scal + SC_ENER;
@@ -927,6 +938,16 @@ __global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src,
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+// Energies and error flags of many instances into one buffer (one read-back).
+__global__ void k_gather(const double *const *__restrict__ scal, int count, int width, double *__restrict__ dst)
+{
+    const int i = blockIdx.x;
+    const int k = threadIdx.x;
+    if (i >= count) return;
+    if (k < 25) dst[(size_t)i * width + k] = scal[i][SC_ENER + k];
+    else if (k == 25) dst[(size_t)i * width + k] = scal[i][SC_ERR];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -978,7 +999,7 @@ int launch_overlap_psi(const Plan &pl, hipStream_t st)
 
 int launch_overlap_finalize(const Plan &pl, hipStream_t st)
 {
-    k_overlap_finalize<<<grid_inst(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_overlap_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -993,7 +1014,7 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st)
 
 int launch_multipole_finalize(const Plan &pl, hipStream_t st)
 {
-    k_multipole_finalize<<<grid_inst(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_multipole_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -1023,7 +1044,7 @@ int launch_residual(const Plan &pl, hipStream_t st)
 
 int launch_residual_finalize(const Plan &pl, hipStream_t st)
 {
-    k_residual_finalize<<<grid_inst(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_residual_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -1074,7 +1095,7 @@ int launch_energy_terms(const Plan &pl, hipStream_t st)
 
 int launch_energy_finalize(const Plan &pl, hipStream_t st)
 {
-    k_energy_finalize<<<grid_inst(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_energy_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -1085,6 +1106,13 @@ int launch_stage_orbitals(const Plan &pl, hipStream_t st)
         k_stage_orbitals<typename TG::T><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
         LAUNCH_CHECK();
     });
+}
+
+int launch_gather(const double *const *scal, int count, int width, double *dst, hipStream_t st)
+{
+    if (count <= 0) return 0;
+    k_gather<<<count, 32, 0, st>>>(scal, count, width, dst);
+    LAUNCH_CHECK();
 }
 
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)

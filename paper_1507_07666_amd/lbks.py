@@ -84,6 +84,7 @@ SIGNATURES = {
     "lbks_batch_relax": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int32),
                                    POINTER(c_int64)]),
     "lbks_batch_size": (c_int32, [c_void_p]),
+    "lbks_batch_stream": (c_void_p, [c_void_p]),
     "lbks_batch_destroy": (None, [c_void_p]),
 }
 
@@ -243,11 +244,12 @@ def params_for(system, **kw) -> lbks_params:
 class Solver:
     """One solve context on one GPU."""
 
-    def __init__(self, p: lbks_params, device: int = 0, use_torch: bool = True, stream=None):
+    def __init__(self, p: lbks_params, device: int = 0, use_torch: bool = True, stream=None,
+                 use_allocator: bool = True):
         self._keep = []
         dev = None
         if use_torch:
-            dev, self._keep = torch_device_binding(device, stream)
+            dev, self._keep = torch_device_binding(device, stream, use_allocator)
         self.p = p
         self.ctx = lbks_create(p, dev)
         self.n_orb = p.n_orb
@@ -306,3 +308,61 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Many solves advanced together: one launch per kernel per group of alike
+    solves, each step captured in a HIP graph (lbks_batch_* in the C ABI)."""
+
+    def __init__(self, device: int = 0, use_torch_allocator: bool = True):
+        import torch
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)      # default priority
+        dev, self._keep = torch_device_binding(device, self.stream, use_torch_allocator)
+        self._use_alloc = use_torch_allocator
+        out = c_void_p()
+        rc = load().lbks_batch_create(ctypes.byref(dev), ctypes.byref(out))
+        if rc != 0:
+            raise LbksError(rc, "lbks_batch_create failed")
+        self.handle = out
+        self.solvers = []
+
+    def add(self, p: lbks_params) -> "Solver":
+        s = Solver(p, device=self.device, stream=self.stream, use_allocator=self._use_alloc)
+        rc = load().lbks_batch_attach(self.handle, s.ctx)
+        _check(s.ctx, rc)
+        self.solvers.append(s)
+        return s
+
+    def add_system(self, system, set_nuclei=True, **kw) -> "Solver":
+        s = self.add(params_for(system, **kw))
+        if set_nuclei:
+            s.set_nuclei(system.Z, system.R)
+        return s
+
+    def remove(self, s: "Solver"):
+        _check(s.ctx, load().lbks_batch_detach(self.handle, s.ctx))
+        self.solvers.remove(s)
+
+    def relax(self, max_steps, dE_tol=0.0, check_every=100):
+        m = len(self.solvers)
+        st = (c_int32 * max(1, m))()
+        steps = (c_int64 * max(1, m))()
+        rc = load().lbks_batch_relax(self.handle, int(max_steps), float(dE_tol), int(check_every), st, steps)
+        if rc < 0:
+            raise LbksError(rc, "lbks_batch_relax failed")
+        return list(st[:m]), list(steps[:m])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lbks_batch_destroy(self.handle)
+            self.handle = None
+        for s in self.solvers:
+            s.close()
+        self.solvers = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

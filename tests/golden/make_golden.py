@@ -1,0 +1,79 @@
+"""Write converged FP64 oracle references for the full-size workloads.
+
+Calls only oracle/ and the seeded input generators; nothing here touches the
+GPU library.  Usage:  python tests/golden/make_golden.py ne96 ch4 ...
+Each run writes tests/golden/<name>.json (relaxation rule, steps, energies,
+eigenvalues, density norms and seeded node samples) and <name>_rho.npz (the
+density on every second node per axis, float32).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1507_07666_amd import inputs as I  # noqa: E402
+
+# name -> (system factory, dE_tol per check, check_every, max_steps)
+RUNS = {
+    "ne96": (I.ne_atom, 1e-8, 100, 40000),
+    "ch4": (I.ch4, 1e-7, 100, 40000),
+    "he32": (I.he_atom, 0.0, 2000, 2000),
+}
+for i, s in enumerate(I.h2o_batch(64)):
+    if i in (0, 1, 2, 3, 4, 5, 6, 7):
+        RUNS[f"h2o_{i}"] = (lambda s=s: s, 1e-7, 100, 40000)
+
+N_SAMPLES = 4096
+
+
+def sample_nodes(n_sites, seed=12345):
+    return np.sort(I.splitmix64(seed, np.arange(N_SAMPLES, dtype=np.uint64)) % np.uint64(n_sites)).astype(np.int64)
+
+
+def run(name):
+    factory, tol, every, max_steps = RUNS[name]
+    system = factory()
+    t0 = time.time()
+    o = O.oracle_for(system)
+    log = []
+
+    def progress(steps, e):
+        log.append((steps, e))
+        print(f"[{name}] step {steps} E {e:.12f} ({time.time() - t0:.0f}s)", flush=True)
+
+    rc, steps = o.relax(max_steps, tol, every, progress=progress)
+    e = o.energies(converge_poisson=True)
+    psihat, rho = o.state()
+    nx, ny, nz = system.dims
+    idx = sample_nodes(system.n_sites)
+    out = {
+        "name": name, "system": system.name, "dims": list(system.dims), "h": system.h,
+        "Z": list(system.Z), "R": [list(r) for r in system.R], "n_elec": system.n_elec,
+        "n_orb": system.n_orb, "softening": system.softening, "seed": system.seed,
+        "rule": {"dE_tol": tol, "check_every": every, "max_steps": max_steps},
+        "rc": rc, "steps": steps,
+        "energies": {k: float(getattr(e, k)) for k in ("e_total", "e_kin", "e_ext", "e_hartree", "e_x",
+                                                          "e_c", "e_nn", "n_electrons", "poisson_residual")},
+        "eps": [float(x) for x in e.eps],
+        "rho_l2": float(np.linalg.norm(rho)), "rho_max": float(rho.max()),
+        "sample_nodes": idx.tolist(), "rho_samples": rho[idx].tolist(),
+        "trace": log, "wall_s": time.time() - t0,
+        "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f)
+    sub = rho.reshape(nz, ny, nx)[::2, ::2, ::2].astype(np.float32)
+    np.savez_compressed(os.path.join(HERE, f"{name}_rho.npz"), rho_sub=sub)
+    print(f"[{name}] done rc={rc} steps={steps} E={e.e_total:.12f} in {time.time() - t0:.0f}s", flush=True)
+
+
+if __name__ == "__main__":
+    for n in sys.argv[1:]:
+        run(n)

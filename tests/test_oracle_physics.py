@@ -176,7 +176,21 @@ def test_relax_stopping_rule(oracle_mod):
     rc, steps = o.relax(5000, dE_tol=1e-9, check_every=25)
     assert rc == 0 and steps % 25 == 0 and steps < 5000
     rc2, steps2 = o.relax(5000, dE_tol=1e-9, check_every=25)
-    assert rc2 == 0 and steps2 == 50      # already converged: two checks
+    assert rc2 == 0 and steps2 == 25      # history kept across calls: one more check
+    o.energies(converge_poisson=True)     # changes the state: history forgotten
+    rc3, steps3 = o.relax(5000, dE_tol=1e-9, check_every=25)
+    assert rc3 == 0 and steps3 >= 50
+    # splitting a run into calls of whole chunks changes nothing
+    a = O.oracle_for(s)
+    b = O.oracle_for(s)
+    ra = a.relax(5000, dE_tol=1e-9, check_every=25)
+    tot = 0
+    while True:
+        rb, nb = b.relax(50, dE_tol=1e-9, check_every=25)
+        tot += nb
+        if rb == 0:
+            break
+    assert ra == (0, tot) and a.energies(False).e_total == b.energies(False).e_total
 
 
 def test_nuclear_repulsion_closed_form(oracle_mod):
