@@ -96,6 +96,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default update-kernel variant")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: time the library's plain copy kernel (bandwidth calibration)")
     ap.add_argument("--copy-mib", type=int, default=678, help="bytes read (= written) by one copy launch")
@@ -121,6 +122,7 @@ def main():
 
     if args.warmup:
         solver.relax(args.warmup)
+    variant, tune_ms = (solver.variant(), None) if args.no_autotune else solver.autotune(reps=5, force=True)
     torch.cuda.synchronize()
     if not args.no_timing:
         solver.set_timing(True)
@@ -151,6 +153,7 @@ def main():
                                f"softening {system.softening}, {system.n_orb} orbitals, "
                                f"{args.precision} {args.scheme}, seed {system.seed}",
                    "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
+                   "update_variant": variant, "autotune_ms": tune_ms,
                    "parallelism": "single GPU"},
         "e_total": e["e_total"],
     }

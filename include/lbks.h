@@ -83,7 +83,7 @@ extern "C" {
 #define LBKS_SCHEME_COLLAPSED 1
 
 typedef struct lbks_params {
-    int32_t N[3];            /* nodes per axis, each in [4, 1024] */
+    int32_t N[3];            /* nodes per axis, each in [4, 1024]; N0 N1 N2 < 2^29 */
     double h;                /* node spacing (bohr) */
     int32_t n_orb;           /* orbitals, 1..LBKS_MAX_ORB */
     int32_t n_elec;          /* electrons; occupations 2,2,...,n_elec-2(n_orb-1) */
@@ -217,6 +217,22 @@ size_t lbks_estimate_bytes(const lbks_params *p);
  * synchronises the stream.  kernel: 0 = stream-collide. */
 int lbks_set_timing(lbks_ctx *ctx, int32_t enable);
 int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Update-kernel variants: bit 0 computes the per-workgroup overlap partial
+ * S = Phi^T Phi on the matrix cores (V_MFMA_F64_16X16X4F64) instead of a wave
+ * butterfly, bit 1 compiles the kernel for 8 waves per SIMD.  Every variant
+ * computes the same arithmetic; only the overlap's summation order differs.
+ * Defaults: 0 for FP64, 3 for FP32. */
+int lbks_set_variant(lbks_ctx *ctx, int32_t variant);
+int lbks_get_variant(const lbks_ctx *ctx);
+
+/* Time every update-kernel variant `reps` times on the context's current state
+ * and keep the fastest (state unchanged).  Choices are cached per (precision,
+ * orbital bucket, orthogonalisation, scheme, node count) for the process; with
+ * force = 0 a cached choice is reused without timing.  chosen (may be NULL)
+ * receives the variant, avg_ms (NULL, or 4 doubles) the per-launch times
+ * (-1 when the cache answered).  LBKS_E_STATE if no potential is set. */
+int lbks_autotune(lbks_ctx *ctx, int32_t reps, int32_t force, int32_t *chosen, double *avg_ms);
 
 /* Plain device-to-device copy of `bytes` on `stream` with the library's own
  * copy kernel (device pointers, 16-byte aligned); used to calibrate memory

@@ -12,6 +12,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -61,7 +64,7 @@ struct lbks_ctx {
 
 // One launch group of a batch: members sharing every template and sequence choice.
 struct BatchGroup {
-    int precision = 0, no = 1, scheme = 0, hartree = 1, sweeps = 2;
+    int precision = 0, no = 1, scheme = 0, hartree = 1, sweeps = 2, variant = 0;
     bool wmode = false;
     std::vector<int> members;   // indices into lbks_batch::members
     Plan plan{};
@@ -144,7 +147,10 @@ int validate(const lbks_params *p, std::string &why)
     if (!p) { why = "params is NULL"; return LBKS_E_INVAL; }
     for (int a = 0; a < 3; ++a)
         if (p->N[a] < 4 || p->N[a] > 1024) { why = "grid size out of [4, 1024]"; return LBKS_E_INVAL; }
-    if ((double)p->N[0] * p->N[1] * p->N[2] >= 2147483647.0) { why = "grid too large"; return LBKS_E_INVAL; }
+    if ((double)p->N[0] * p->N[1] * p->N[2] * 8.0 >= 4294967296.0) {
+        why = "grid too large: nodes x 8 bytes must stay below 2^32";
+        return LBKS_E_INVAL;
+    }
     if (!(p->h > 0.0) || !isfinite(p->h)) { why = "h must be positive"; return LBKS_E_INVAL; }
     if (p->n_orb < 1 || p->n_orb > LBKS_MAX_ORB) { why = "n_orb out of [1, 16]"; return LBKS_E_INVAL; }
     if (p->n_elec < 1 || p->n_elec > 2 * p->n_orb || p->n_elec <= 2 * (p->n_orb - 1)) {
@@ -522,6 +528,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;
     pl.n_inst = 1;
+    pl.variant = default_variant(pl.precision);
 
     int rc = 0;
     auto bail = [&](int code) {
@@ -771,6 +778,107 @@ extern "C" int lbks_copy_kernel(void *dst, const void *src, size_t bytes, void *
     return e ? LBKS_E_HIP : 0;
 }
 
+extern "C" int lbks_set_variant(lbks_ctx *c, int32_t variant)
+{
+    if (!c || variant < 0 || variant >= N_VARIANTS) return LBKS_E_INVAL;
+    c->plan.variant = variant;
+    mark_batch_dirty(c);
+    return 0;
+}
+
+extern "C" int lbks_get_variant(const lbks_ctx *c)
+{
+    return c ? c->plan.variant : LBKS_E_INVAL;
+}
+
+namespace {
+
+struct TuneKey {
+    int precision, no, wmode, scheme, nsite;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(precision, no, wmode, scheme, nsite) < std::tie(o.precision, o.no, o.wmode, o.scheme, o.nsite);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tuned;
+
+}  // namespace
+
+extern "C" int lbks_autotune(lbks_ctx *c, int32_t reps, int32_t force, int32_t *chosen, double *avg_ms)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    if (reps < 1) reps = 1;
+    const TuneKey key{c->plan.precision, c->plan.no, c->plan.wmode ? 1 : 0, c->p.scheme, c->h.nsite};
+    if (!force) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            c->plan.variant = it->second;
+            mark_batch_dirty(c);
+            if (chosen) *chosen = it->second;
+            if (avg_ms)
+                for (int v = 0; v < N_VARIANTS; ++v) avg_ms[v] = -1.0;
+            return 0;
+        }
+    }
+    const bool pops = c->p.scheme == LBKS_SCHEME_POPULATIONS;
+    const size_t state_bytes = (size_t)c->p.n_orb * c->h.nsite * (c->plan.precision ? 4 : 8);
+    // derived fields of the current state (the Hartree potential is not touched)
+    KCHK(c, plan_orthonormalise(c->plan, c->stream));
+    KCHK(c, launch_potential(c->plan, 0, c->stream));
+    if (!pops) HIPCHK(c, hipMemcpyAsync(c->h.stage, c->h.psi, state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int saved = c->plan.variant;
+    int best = saved;
+    double best_ms = 1e300;
+    double ms_v[N_VARIANTS];
+    int rc = 0;
+    for (int v = 0; v < N_VARIANTS && !rc; ++v) {
+        c->plan.variant = v;
+        // one untimed launch, then `reps` timed ones; each launch recomputes the same
+        // output from the same inputs
+        if (plan_update(c->plan, c->p.scheme, c->parity, c->stream)) rc = LBKS_E_HIP;
+        if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = LBKS_E_HIP;
+        for (int k = 0; k < reps && !rc; ++k)
+            if (plan_update(c->plan, c->p.scheme, c->parity, c->stream)) rc = LBKS_E_HIP;
+        if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = LBKS_E_HIP;
+        float ms = 0.f;
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = LBKS_E_HIP;
+        ms_v[v] = ms / reps;
+        if (!rc && ms_v[v] < best_ms) {
+            best_ms = ms_v[v];
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->plan.variant = rc ? saved : best;
+    // restore what the timed launches overwrote: the moment and overlap partials of
+    // the current populations, or the orbital state of the collapsed scheme
+    if (pops) {
+        KCHK(c, launch_moment(c->plan, c->parity, c->stream));
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->h.psi, c->h.stage, state_bytes, hipMemcpyDeviceToDevice, c->stream));
+        KCHK(c, launch_overlap_psi(c->plan, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (rc) return fail(c, rc, "autotune launch failed");
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = best;
+    }
+    mark_batch_dirty(c);
+    if (chosen) *chosen = best;
+    if (avg_ms)
+        for (int v = 0; v < N_VARIANTS; ++v) avg_ms[v] = ms_v[v];
+    return 0;
+}
+
 // ================================================================ batches
 
 namespace {
@@ -850,10 +958,11 @@ int batch_build(lbks_batch *b)
         key.scheme = c->p.scheme;
         key.hartree = c->p.hartree;
         key.sweeps = c->p.poisson_sweeps;
+        key.variant = c->plan.variant;
         BatchGroup *g = nullptr;
         for (BatchGroup &x : b->groups)
             if (x.precision == key.precision && x.no == key.no && x.wmode == key.wmode && x.scheme == key.scheme &&
-                x.hartree == key.hartree && x.sweeps == key.sweeps)
+                x.hartree == key.hartree && x.sweeps == key.sweeps && x.variant == key.variant)
                 g = &x;
         if (!g) {
             b->groups.push_back(key);
@@ -936,6 +1045,7 @@ int batch_build(lbks_batch *b)
         pl.no = g.no;
         pl.wmode = g.wmode;
         pl.n_inst = (int)g.members.size();
+        pl.variant = g.variant;
     }
     const double **hs = (const double **)(host.data() + scal_off);
     for (int i = 0; i < m; ++i) hs[i] = b->members[i]->h.scal;

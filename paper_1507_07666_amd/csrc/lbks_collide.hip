@@ -1,0 +1,196 @@
+// lbks_collide.hip -- the lattice Boltzmann update kernels (stream-collide of
+// the populations, and the equivalent omega = 1 update of the orbital fields),
+// each compiled in four variants for the autotuner: overlap partial by wave
+// butterfly or on the matrix cores, and compiler-chosen or 8-wave occupancy.
+#include "lbks_device.h"
+
+namespace lbks {
+
+// --------------------------------------------------------- stream-collide
+
+// Pull form of the lattice Boltzmann equation with the orthogonalisation and
+// potential sources: the population entering node r along v_p is the
+// post-collision population of r - v_p,
+//   f_jp(r; t+1) = (1 - omega) g_jp + omega xi_p psi*_j - dt chi_p V psi_hat_j  at r - v_p,
+// g_jp = sum_{l<=j} f_lp C_lj, and zero when r - v_p is outside the box.  The new
+// moment psi_j = sum_p f_jp and the overlap partials psi_j psi_k are fused.
+// Variant bits: 1 = overlap partial on the matrix cores (else wave butterfly),
+// 2 = ask the compiler for 8 waves per SIMD (else its own register budget).
+template <int V>
+__device__ __forceinline__ constexpr int waves_hint() { return (V & 2) ? 8 : 1; }
+
+template <typename T, int NO, int V>
+__device__ __forceinline__ void overlap_partial_v(const T (&acc)[NO], int n, double *out, int stride)
+{
+    if constexpr (V & 1) {
+        overlap_partial<T, NO>(acc, n, out, stride);
+    } else {
+        double prod[NO * (NO + 1) / 2];
+        int q = 0;
+#pragma unroll
+        for (int j = 0; j < NO; ++j)
+#pragma unroll
+            for (int k = 0; k <= j; ++k) prod[q++] = (double)acc[j] * (double)acc[k];
+        block_sum_store(prod, npair_of(n), out, stride);
+    }
+}
+
+template <typename T, int NO, bool W, int V>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V>(), 8))) void k_stream_collide(const InstDesc *__restrict__ descs,
+                                                       const int2 *__restrict__ tiles, int parity)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int n = orbitals<NO>(d);
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const long long N = d.nsite;
+    const unsigned plane = (unsigned)N * (unsigned)sizeof(T);
+    const int s = tr.tile * BS + threadIdx.x;
+    const bool valid = s < d.nsite;
+    const void *fs = parity ? d.f1 : d.f0;
+    void *fd = parity ? d.f0 : d.f1;
+    const T a = (T)(1.0 - d.omega);
+    const T om = (T)d.omega;
+    const T dt = (T)d.dt;
+    T c[NO][NO];
+#pragma unroll
+    for (int l = 0; l < NO; ++l)
+#pragma unroll
+        for (int j = 0; j < NO; ++j) c[l][j] = (T)d.C[l * MAXO + j];
+    const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
+    const unsigned off = (unsigned)s * (unsigned)sizeof(T);
+    T acc[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) acc[j] = (T)0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const int vx = VX(p), vy = VY(p), vz = VZ(p);
+        const bool ok = valid && (unsigned)(x - vx) < (unsigned)nx && (unsigned)(y - vy) < (unsigned)ny &&
+                        (unsigned)(z - vz) < (unsigned)nz;
+        // byte offset of the source node r - v_p; when it falls outside the box the
+        // loads are discarded by `ok` (and read 0 if beyond the plane)
+        const unsigned src = off - (unsigned)((vx + nx * (vy + ny * vz)) * (int)sizeof(T));
+        T fl[NO];
+#pragma unroll
+        for (int l = 0; l < NO; ++l)
+            fl[l] = (l < n) ? bload<T, BUF_NT>(plane_rsrc(fs, ((long long)l * Q + p) * N, sizeof(T), plane), src)
+                            : (T)0;
+        const T vn = bload<T, 0>(plane_rsrc(d.V, 0, sizeof(T), plane), src);
+        const T cp = om * (T)d.xi[p];
+        const T dp = dt * (T)d.chi[p] * vn;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            if (j < n) {
+                const T hat = bload<T, 0>(plane_rsrc(d.psihat, (long long)j * N, sizeof(T), plane), src);
+                T o;
+                if (W) {
+                    const T star = bload<T, 0>(plane_rsrc(d.psistar, (long long)j * N, sizeof(T), plane), src);
+                    o = a * (c[j][j] * fl[j]) + cp * star - dp * hat;
+                } else {
+                    T g = (T)0;
+#pragma unroll
+                    for (int l = 0; l <= j; ++l) g += c[l][j] * fl[l];
+                    o = a * g + (cp - dp) * hat;
+                }
+                o = ok ? o : (T)0;
+                // populations are read once per step: stream them past the caches
+                bstore<T, BUF_NT>(o, plane_rsrc(fd, ((long long)j * Q + p) * N, sizeof(T), plane), off);
+                acc[j] += o;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NO; ++j)
+        if (j < n) bstore<T, 0>(acc[j], plane_rsrc(d.psi, (long long)j * N, sizeof(T), plane), off);
+    overlap_partial_v<T, NO, V>(acc, n, d.s_part + tr.tile, d.ntile);
+}
+
+// omega = 1 without populations: psi_j(r) <- sum_p [xi_p psi*_j - dt chi_p V psi_hat_j](r - v_p),
+// exactly the moment of the population update at omega = 1.
+template <typename T, int NO, bool W, int V>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V>(), 8))) void k_collapsed(const InstDesc *__restrict__ descs,
+                                                  const int2 *__restrict__ tiles)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int n = orbitals<NO>(d);
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int s = tr.tile * BS + threadIdx.x;
+    const bool valid = s < d.nsite;
+    T acc[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) acc[j] = (T)0;
+    if (valid) {
+        const size_t N = (size_t)d.nsite;
+        const T *__restrict__ ph = (const T *)d.psihat;
+        const T *__restrict__ pst = (const T *)d.psistar;
+        const T *__restrict__ Vp = (const T *)d.V;
+        const T dt = (T)d.dt;
+        const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const int vx = VX(p), vy = VY(p), vz = VZ(p);
+            const bool ok = (unsigned)(x - vx) < (unsigned)nx && (unsigned)(y - vy) < (unsigned)ny &&
+                            (unsigned)(z - vz) < (unsigned)nz;
+            if (ok) {
+                const int src = s - (vx + nx * (vy + ny * vz));
+                const T cp = (T)d.xi[p];
+                const T dp = dt * (T)d.chi[p] * Vp[src];
+#pragma unroll
+                for (int j = 0; j < NO; ++j) {
+                    if (j < n) {
+                        if (W) acc[j] += cp * pst[(size_t)j * N + src] - dp * ph[(size_t)j * N + src];
+                        else acc[j] += (cp - dp) * ph[(size_t)j * N + src];
+                    }
+                }
+            }
+        }
+        T *psi = (T *)d.psi;
+#pragma unroll
+        for (int j = 0; j < NO; ++j)
+            if (j < n) psi[(size_t)j * N + s] = acc[j];
+    }
+    overlap_partial_v<T, NO, V>(acc, n, d.s_part + tr.tile, d.ntile);
+}
+
+template <int V>
+static int launch_stream_collide_v(const Plan &pl, int parity, hipStream_t st)
+{
+    return dispatch_tnw(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_stream_collide<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, parity);
+        LAUNCH_CHECK();
+    });
+}
+
+template <int V>
+static int launch_collapsed_v(const Plan &pl, hipStream_t st)
+{
+    return dispatch_tnw(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_collapsed<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
+        LAUNCH_CHECK();
+    });
+}
+
+int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
+{
+    switch (pl.variant & 3) {
+    case 0: return launch_stream_collide_v<0>(pl, parity, st);
+    case 1: return launch_stream_collide_v<1>(pl, parity, st);
+    case 2: return launch_stream_collide_v<2>(pl, parity, st);
+    default: return launch_stream_collide_v<3>(pl, parity, st);
+    }
+}
+
+int launch_collapsed_update(const Plan &pl, hipStream_t st)
+{
+    switch (pl.variant & 3) {
+    case 0: return launch_collapsed_v<0>(pl, st);
+    case 1: return launch_collapsed_v<1>(pl, st);
+    case 2: return launch_collapsed_v<2>(pl, st);
+    default: return launch_collapsed_v<3>(pl, st);
+    }
+}
+
+}  // namespace lbks

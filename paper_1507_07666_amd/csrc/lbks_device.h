@@ -1,0 +1,359 @@
+// lbks_device.h -- device helpers shared by the kernel translation units of
+// liblbks.so: the D3Q19 velocity set, workgroup-to-tile mapping, fixed-order
+// reductions (wave butterfly, column sums, the matrix-core overlap partial),
+// buffer and global-address-space access, local exchange-correlation, and the
+// template dispatch on (precision, orbital bucket, orthogonalisation mode).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "lbks_kernels.h"
+
+namespace lbks {
+
+// ------------------------------------------------------------------ lattice
+
+// D3Q19 velocities: 0 rest; 1..6 faces (+x -x +y -y +z -z); 7..10 xy edges
+// (++ -+ +- --); 11..14 xz edges (++ -+ +- --); 15..18 yz edges (++ -+ +- --).
+__host__ __device__ constexpr int VX(int p)
+{
+    return (p == 1 || p == 7 || p == 9 || p == 11 || p == 13) ? 1
+         : (p == 2 || p == 8 || p == 10 || p == 12 || p == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int VY(int p)
+{
+    return (p == 3 || p == 7 || p == 8 || p == 15 || p == 17) ? 1
+         : (p == 4 || p == 9 || p == 10 || p == 16 || p == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int VZ(int p)
+{
+    return (p == 5 || p == 11 || p == 12 || p == 15 || p == 16) ? 1
+         : (p == 6 || p == 13 || p == 14 || p == 17 || p == 18) ? -1 : 0;
+}
+
+// ---------------------------------------------------------------- helpers
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD
+// works on one contiguous range of tiles (neighbour planes stay in its L2).
+__device__ __forceinline__ int xcd_remap(int b, int nblk)
+{
+    const int X = 8;
+    const int xcd = b % X, idx = b / X, q = nblk / X, r = nblk % X;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+struct TileRef {
+    int inst, tile;
+};
+
+__device__ __forceinline__ TileRef resolve(const int2 *table)
+{
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    if (table) {
+        const int2 t = table[b];
+        return {t.x, t.y};
+    }
+    return {0, b};
+}
+
+__device__ __forceinline__ int resolve_inst(const int *list)
+{
+    return list ? list[blockIdx.x] : (int)blockIdx.x;
+}
+
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Sum v[0..nv) over the workgroup; thread q < nv writes its total to out[q * stride].
+template <int NV>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], int nv, double *out, int stride)
+{
+    __shared__ double red[BS / 64][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q < nv) {
+            const double x = wave_sum(v[q]);
+            if (lane == 0) red[wave][q] = x;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; ++w) s += red[w][threadIdx.x];
+        out[(size_t)threadIdx.x * stride] = s;
+    }
+}
+
+constexpr int FB = 1024;   // threads of the per-instance finalize kernels
+
+// Column sums out[q] = sum_t part[q * ntile + t] for q < nq, in a fixed order
+// (each thread strides the tiles, then the waves are summed in order).  The
+// partial arrays hold whole chunks of RCH columns (unused ones stay zero), so
+// every load is unconditional and all of a thread's loads are in flight at once.
+// `out` is LDS; every thread of the FB-wide workgroup must call this.
+static __device__ void reduce_columns(const double *__restrict__ part, int ntile, int nq, double *out)
+{
+    constexpr int U = 4;   // tiles per thread per round
+    __shared__ double red[FB / 64][RCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int q0 = 0; q0 < nq; q0 += RCH) {
+        const double *col = part + (size_t)q0 * ntile;
+        double acc[RCH];
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) acc[c] = 0.0;
+        for (int t0 = 0; t0 < ntile; t0 += U * FB) {
+            double v[U][RCH];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int t = t0 + k * FB + (int)threadIdx.x;
+                const int tc = t < ntile ? t : ntile - 1;
+#pragma unroll
+                for (int c = 0; c < RCH; ++c) v[k][c] = col[(size_t)c * ntile + tc];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const double w = (t0 + k * FB + (int)threadIdx.x) < ntile ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < RCH; ++c) acc[c] += w * v[k][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < RCH; ++c) {
+            const double x = wave_sum(acc[c]);
+            if (lane == 0) red[wave][c] = x;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < RCH && q0 + (int)threadIdx.x < nq) {
+            double sum = 0.0;
+            for (int w = 0; w < FB / 64; ++w) sum += red[w][threadIdx.x];
+            out[q0 + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double node_coord(int i, int n, double h)
+{
+    return ((double)i - 0.5 * (double)(n - 1)) * h;
+}
+
+__device__ __forceinline__ int npair_of(int n) { return n * (n + 1) / 2; }
+
+// Orbital count inside a kernel instantiated for bucket NO: buckets 1..5 hold
+// exactly NO orbitals, so the count is a compile-time constant there and every
+// per-orbital guard folds away; buckets 8 and 16 read it from the descriptor.
+template <int NO>
+__device__ __forceinline__ int orbitals(const InstDesc &d)
+{
+    return NO <= 5 ? NO : d.n_orb;
+}
+
+// Global-memory views of descriptor pointers.  Buffers reached through the
+// descriptor are generic pointers to the compiler, which would address every load
+// with a 64-bit per-lane flat address; in the global address space a load is a
+// scalar (uniform) plane base plus one 32-bit per-lane byte offset.
+#define GAS __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ const GAS T *gplane(const void *base, long long elems)
+{
+    return (const GAS T *)base + elems;
+}
+template <typename T>
+__device__ __forceinline__ GAS T *gplane_w(void *base, long long elems)
+{
+    return (GAS T *)base + elems;
+}
+template <typename T>
+__device__ __forceinline__ const GAS T *at_bytes(const GAS T *plane, unsigned off_bytes)
+{
+    return (const GAS T *)((const GAS char *)plane + off_bytes);
+}
+template <typename T>
+__device__ __forceinline__ GAS T *at_bytes_w(GAS T *plane, unsigned off_bytes)
+{
+    return (GAS T *)((GAS char *)plane + off_bytes);
+}
+
+// Buffer access: a plane is a scalar resource (base, byte range) and a node a
+// 32-bit per-lane byte offset, so no per-load 64-bit address is formed.  An offset
+// outside the plane's range reads 0 and drops stores (hardware range check).
+constexpr int BUF_WORD3 = 0x00020000;   // gfx9-family raw buffer format word
+constexpr int BUF_NT = 2;               // non-temporal (streaming) cache policy
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, long long elems, int elem_bytes,
+                                                             unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((char *)base + elems * elem_bytes, 0, (int)bytes, BUF_WORD3);
+}
+
+template <typename T, int AUX>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX));
+}
+
+template <typename T, int AUX>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(
+            __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, (int)off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(
+            __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r, (int)off, 0, AUX);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Overlap partial of one workgroup, S_jk = sum over its nodes of psi_j psi_k
+// (k <= j < n), as Phi^T Phi on the matrix cores: per wave the 64 nodes form 16
+// blocks of 4, each one V_MFMA_F64_16X16X4F64 with Phi^T (16 orbitals x 4 nodes)
+// as A and Phi as B; lane l, register r of the result holds S(l % 16, 4r + l / 16).
+// The four waves are then summed in order; thread q < npair writes out[q * stride]
+// in the packed order q = j (j + 1) / 2 + k.  Every thread must call this.
+template <typename T, int NO>
+__device__ void overlap_partial(const T (&acc)[NO], int n, double *out, int stride)
+{
+    __shared__ double phi[BS / 64][64][NO + 1];
+    __shared__ double red[BS / 64][NO][NO];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) phi[wave][lane][o] = (double)acc[o];
+    __syncthreads();
+    v4d S = {0.0, 0.0, 0.0, 0.0};
+    const int o = lane & 15, k = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const double a = o < NO ? phi[wave][4 * m + k][o] : 0.0;
+        S = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, S, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int col = 4 * r + k;
+        if (o < NO && col < NO) red[wave][o][col] = S[r];
+    }
+    __syncthreads();
+    const int q = threadIdx.x;
+    if (q < npair_of(n)) {
+        int j = 0;
+        while ((j + 1) * (j + 2) / 2 <= q) ++j;
+        const int kk = q - j * (j + 1) / 2;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < BS / 64; ++w) sum += red[w][j][kk];
+        out[(size_t)q * stride] = sum;
+    }
+}
+
+// Local exchange-correlation per electron (e*) and potential (v* = d(rho e*)/d rho):
+// Slater exchange; correlation of Lee-Yang-Parr at zero gradient,
+// e_c = -a (1 + b C_F exp(-c u)) / (1 + d u), u = rho^(-1/3); or Perdew-Zunger 1981.
+static __device__ void xc_eval(int kind, double rho, double floor, double &ex, double &ec, double &vx,
+                        double &vc)
+{
+    ex = ec = vx = vc = 0.0;
+    if (kind == 0 || !(rho >= floor) || !(rho > 0.0)) return;
+    const double PI = 3.14159265358979323846;
+    vx = -cbrt(3.0 * rho / PI);
+    ex = 0.75 * vx;
+    if (kind == 2) {
+        const double a = 0.04918, b = 0.132, c = 0.2533, d = 0.349;
+        const double CF = 2.8712340001881915;   // (3/10)(3 pi^2)^(2/3)
+        const double u = 1.0 / cbrt(rho);
+        const double e = exp(-c * u);
+        const double num = 1.0 + b * CF * e, den = 1.0 + d * u;
+        const double g = num / den;
+        const double gp = (-b * CF * c * e * den - d * num) / (den * den);
+        ec = -a * g;
+        vc = -a * (g - (u / 3.0) * gp);
+    } else if (kind == 3) {
+        const double rs = cbrt(3.0 / (4.0 * PI * rho));
+        if (rs >= 1.0) {
+            const double gam = -0.1423, b1 = 1.0529, b2 = 0.3334;
+            const double sq = sqrt(rs);
+            const double den = 1.0 + b1 * sq + b2 * rs;
+            ec = gam / den;
+            vc = ec * (1.0 + (7.0 / 6.0) * b1 * sq + (4.0 / 3.0) * b2 * rs) / den;
+        } else {
+            const double A = 0.0311, B = -0.048, Cc = 0.0020, Dd = -0.0116;
+            const double lr = log(rs);
+            ec = A * lr + B + Cc * rs * lr + Dd * rs;
+            vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * Cc * rs * lr + (2.0 * Dd - Cc) * rs / 3.0;
+        }
+    }
+}
+
+// --------------------------------------------------------------- dispatch
+
+template <typename TT, int NOO, bool WW>
+struct Tag {
+    using T = TT;
+    static constexpr int NO = NOO;
+    static constexpr bool W = WW;
+};
+
+template <int NO, bool W, typename F>
+int dispatch_t(const Plan &pl, F &f)
+{
+    if (pl.precision) return f(Tag<float, NO, W>{});
+    return f(Tag<double, NO, W>{});
+}
+template <int NO, typename F>
+int dispatch_w(const Plan &pl, F &f)
+{
+    if (pl.wmode) return dispatch_t<NO, true>(pl, f);
+    return dispatch_t<NO, false>(pl, f);
+}
+template <typename F>
+int dispatch_tnw(const Plan &pl, F &&f)
+{
+    switch (pl.no) {
+    case 1: return dispatch_w<1>(pl, f);
+    case 2: return dispatch_w<2>(pl, f);
+    case 3: return dispatch_w<3>(pl, f);
+    case 4: return dispatch_w<4>(pl, f);
+    case 5: return dispatch_w<5>(pl, f);
+    case 8: return dispatch_w<8>(pl, f);
+    default: return dispatch_w<16>(pl, f);
+    }
+}
+template <typename F>
+int dispatch_tn(const Plan &pl, F &&f)
+{
+    switch (pl.no) {
+    case 1: return dispatch_t<1, false>(pl, f);
+    case 2: return dispatch_t<2, false>(pl, f);
+    case 3: return dispatch_t<3, false>(pl, f);
+    case 4: return dispatch_t<4, false>(pl, f);
+    case 5: return dispatch_t<5, false>(pl, f);
+    case 8: return dispatch_t<8, false>(pl, f);
+    default: return dispatch_t<16, false>(pl, f);
+    }
+}
+template <typename F>
+int dispatch_tt(const Plan &pl, F &&f)
+{
+    return dispatch_t<1, false>(pl, f);
+}
+
+
+static inline int grid_site(const Plan &pl) { return pl.tt.site ? pl.tt.n_site : pl.ntile; }
+static inline int grid_ghost(const Plan &pl) { return pl.tt.ghost ? pl.tt.n_ghost : pl.ntile_ghost; }
+static inline int grid_sor(const Plan &pl) { return pl.tt.sor ? pl.tt.n_sor : pl.ntile_sor; }
+static inline int grid_inst(const Plan &pl) { return pl.tt.inst ? pl.tt.n_inst : 1; }
+
+#define LAUNCH_CHECK() return (int)hipGetLastError()
+
+}  // namespace lbks

@@ -80,7 +80,14 @@ struct Plan {
     bool wmode = false;
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0;   // single-instance counts
     int n_inst = 1;
+    int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave occupancy
 };
+
+// Default update-kernel variant per precision (measured on MI355X): FP64 keeps the
+// wave-butterfly overlap at the compiler's occupancy, FP32 takes the matrix-core
+// overlap at 8 waves per SIMD.
+inline int default_variant(int precision) { return precision ? 3 : 0; }
+constexpr int N_VARIANTS = 4;
 
 int orbital_bucket(int n_orb);
 

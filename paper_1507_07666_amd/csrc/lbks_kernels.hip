@@ -16,249 +16,16 @@
 // Every workgroup has BS = 256 threads (4 waves); each thread owns one node.
 // Reductions are fixed-order (wave butterfly, then waves in order, then tiles
 // in order): results do not depend on batch composition and are repeatable.
-#include "lbks_kernels.h"
-
-#include <hip/hip_runtime.h>
-#include <math.h>
+#include "lbks_device.h"
 
 namespace lbks {
-
-// ------------------------------------------------------------------ lattice
-
-// D3Q19 velocities: 0 rest; 1..6 faces (+x -x +y -y +z -z); 7..10 xy edges
-// (++ -+ +- --); 11..14 xz edges (++ -+ +- --); 15..18 yz edges (++ -+ +- --).
-__host__ __device__ constexpr int VX(int p)
-{
-    return (p == 1 || p == 7 || p == 9 || p == 11 || p == 13) ? 1
-         : (p == 2 || p == 8 || p == 10 || p == 12 || p == 14) ? -1 : 0;
-}
-__host__ __device__ constexpr int VY(int p)
-{
-    return (p == 3 || p == 7 || p == 8 || p == 15 || p == 17) ? 1
-         : (p == 4 || p == 9 || p == 10 || p == 16 || p == 18) ? -1 : 0;
-}
-__host__ __device__ constexpr int VZ(int p)
-{
-    return (p == 5 || p == 11 || p == 12 || p == 15 || p == 16) ? 1
-         : (p == 6 || p == 13 || p == 14 || p == 17 || p == 18) ? -1 : 0;
-}
-
-// ---------------------------------------------------------------- helpers
-
-// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD
-// works on one contiguous range of tiles (neighbour planes stay in its L2).
-__device__ __forceinline__ int xcd_remap(int b, int nblk)
-{
-    const int X = 8;
-    const int xcd = b % X, idx = b / X, q = nblk / X, r = nblk % X;
-    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
-struct TileRef {
-    int inst, tile;
-};
-
-__device__ __forceinline__ TileRef resolve(const int2 *table)
-{
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    if (table) {
-        const int2 t = table[b];
-        return {t.x, t.y};
-    }
-    return {0, b};
-}
-
-__device__ __forceinline__ int resolve_inst(const int *list)
-{
-    return list ? list[blockIdx.x] : (int)blockIdx.x;
-}
-
-__device__ __forceinline__ double wave_sum(double x)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
-}
-
-// Sum v[0..nv) over the workgroup; thread q < nv writes its total to out[q * stride].
-template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], int nv, double *out, int stride)
-{
-    __shared__ double red[BS / 64][NV];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            const double x = wave_sum(v[q]);
-            if (lane == 0) red[wave][q] = x;
-        }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nv) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < BS / 64; ++w) s += red[w][threadIdx.x];
-        out[(size_t)threadIdx.x * stride] = s;
-    }
-}
-
-constexpr int FB = 1024;   // threads of the per-instance finalize kernels
-
-// Column sums out[q] = sum_t part[q * ntile + t] for q < nq, in a fixed order
-// (each thread strides the tiles, then the waves are summed in order).  The
-// partial arrays hold whole chunks of RCH columns (unused ones stay zero), so
-// every load is unconditional and all of a thread's loads are in flight at once.
-// `out` is LDS; every thread of the FB-wide workgroup must call this.
-__device__ void reduce_columns(const double *__restrict__ part, int ntile, int nq, double *out)
-{
-    constexpr int U = 4;   // tiles per thread per round
-    __shared__ double red[FB / 64][RCH];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q0 = 0; q0 < nq; q0 += RCH) {
-        const double *col = part + (size_t)q0 * ntile;
-        double acc[RCH];
-#pragma unroll
-        for (int c = 0; c < RCH; ++c) acc[c] = 0.0;
-        for (int t0 = 0; t0 < ntile; t0 += U * FB) {
-            double v[U][RCH];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int t = t0 + k * FB + (int)threadIdx.x;
-                const int tc = t < ntile ? t : ntile - 1;
-#pragma unroll
-                for (int c = 0; c < RCH; ++c) v[k][c] = col[(size_t)c * ntile + tc];
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const double w = (t0 + k * FB + (int)threadIdx.x) < ntile ? 1.0 : 0.0;
-#pragma unroll
-                for (int c = 0; c < RCH; ++c) acc[c] += w * v[k][c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < RCH; ++c) {
-            const double x = wave_sum(acc[c]);
-            if (lane == 0) red[wave][c] = x;
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < RCH && q0 + (int)threadIdx.x < nq) {
-            double sum = 0.0;
-            for (int w = 0; w < FB / 64; ++w) sum += red[w][threadIdx.x];
-            out[q0 + threadIdx.x] = sum;
-        }
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ double node_coord(int i, int n, double h)
-{
-    return ((double)i - 0.5 * (double)(n - 1)) * h;
-}
-
-__device__ __forceinline__ int npair_of(int n) { return n * (n + 1) / 2; }
-
-// Local exchange-correlation per electron (e*) and potential (v* = d(rho e*)/d rho):
-// Slater exchange; correlation of Lee-Yang-Parr at zero gradient,
-// e_c = -a (1 + b C_F exp(-c u)) / (1 + d u), u = rho^(-1/3); or Perdew-Zunger 1981.
-__device__ void xc_eval(int kind, double rho, double floor, double &ex, double &ec, double &vx,
-                        double &vc)
-{
-    ex = ec = vx = vc = 0.0;
-    if (kind == 0 || !(rho >= floor) || !(rho > 0.0)) return;
-    const double PI = 3.14159265358979323846;
-    vx = -cbrt(3.0 * rho / PI);
-    ex = 0.75 * vx;
-    if (kind == 2) {
-        const double a = 0.04918, b = 0.132, c = 0.2533, d = 0.349;
-        const double CF = 2.8712340001881915;   // (3/10)(3 pi^2)^(2/3)
-        const double u = 1.0 / cbrt(rho);
-        const double e = exp(-c * u);
-        const double num = 1.0 + b * CF * e, den = 1.0 + d * u;
-        const double g = num / den;
-        const double gp = (-b * CF * c * e * den - d * num) / (den * den);
-        ec = -a * g;
-        vc = -a * (g - (u / 3.0) * gp);
-    } else if (kind == 3) {
-        const double rs = cbrt(3.0 / (4.0 * PI * rho));
-        if (rs >= 1.0) {
-            const double gam = -0.1423, b1 = 1.0529, b2 = 0.3334;
-            const double sq = sqrt(rs);
-            const double den = 1.0 + b1 * sq + b2 * rs;
-            ec = gam / den;
-            vc = ec * (1.0 + (7.0 / 6.0) * b1 * sq + (4.0 / 3.0) * b2 * rs) / den;
-        } else {
-            const double A = 0.0311, B = -0.048, Cc = 0.0020, Dd = -0.0116;
-            const double lr = log(rs);
-            ec = A * lr + B + Cc * rs * lr + Dd * rs;
-            vc = A * lr + (B - A / 3.0) + (2.0 / 3.0) * Cc * rs * lr + (2.0 * Dd - Cc) * rs / 3.0;
-        }
-    }
-}
-
-// --------------------------------------------------------------- dispatch
-
-template <typename TT, int NOO, bool WW>
-struct Tag {
-    using T = TT;
-    static constexpr int NO = NOO;
-    static constexpr bool W = WW;
-};
-
-template <int NO, bool W, typename F>
-int dispatch_t(const Plan &pl, F &f)
-{
-    if (pl.precision) return f(Tag<float, NO, W>{});
-    return f(Tag<double, NO, W>{});
-}
-template <int NO, typename F>
-int dispatch_w(const Plan &pl, F &f)
-{
-    if (pl.wmode) return dispatch_t<NO, true>(pl, f);
-    return dispatch_t<NO, false>(pl, f);
-}
-template <typename F>
-int dispatch_tnw(const Plan &pl, F &&f)
-{
-    switch (pl.no) {
-    case 1: return dispatch_w<1>(pl, f);
-    case 2: return dispatch_w<2>(pl, f);
-    case 3: return dispatch_w<3>(pl, f);
-    case 4: return dispatch_w<4>(pl, f);
-    case 5: return dispatch_w<5>(pl, f);
-    case 8: return dispatch_w<8>(pl, f);
-    default: return dispatch_w<16>(pl, f);
-    }
-}
-template <typename F>
-int dispatch_tn(const Plan &pl, F &&f)
-{
-    switch (pl.no) {
-    case 1: return dispatch_t<1, false>(pl, f);
-    case 2: return dispatch_t<2, false>(pl, f);
-    case 3: return dispatch_t<3, false>(pl, f);
-    case 4: return dispatch_t<4, false>(pl, f);
-    case 5: return dispatch_t<5, false>(pl, f);
-    case 8: return dispatch_t<8, false>(pl, f);
-    default: return dispatch_t<16, false>(pl, f);
-    }
-}
-template <typename F>
-int dispatch_tt(const Plan &pl, F &&f)
-{
-    return dispatch_t<1, false>(pl, f);
-}
 
 int orbital_bucket(int n)
 {
     return n <= 5 ? n : (n <= 8 ? 8 : 16);
 }
 
-static inline int grid_site(const Plan &pl) { return pl.tt.site ? pl.tt.n_site : pl.ntile; }
-static inline int grid_ghost(const Plan &pl) { return pl.tt.ghost ? pl.tt.n_ghost : pl.ntile_ghost; }
-static inline int grid_sor(const Plan &pl) { return pl.tt.sor ? pl.tt.n_sor : pl.ntile_sor; }
-static inline int grid_inst(const Plan &pl) { return pl.tt.inst ? pl.tt.n_inst : 1; }
 
-#define LAUNCH_CHECK() return (int)hipGetLastError()
 
 // -------------------------------------------------------------- init kernels
 
@@ -331,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_moment(const InstDesc *__restrict__ desc
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
+    const int n = orbitals<NO>(d);
     const int s = tr.tile * BS + threadIdx.x;
     const bool valid = s < d.nsite;
     const size_t N = (size_t)d.nsite;
@@ -350,13 +117,7 @@ __global__ __launch_bounds__(BS) void k_moment(const InstDesc *__restrict__ desc
             }
         }
     }
-    double prod[NO * (NO + 1) / 2];
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < NO; ++j)
-#pragma unroll
-        for (int k = 0; k <= j; ++k) prod[q++] = (double)acc[j] * (double)acc[k];
-    block_sum_store(prod, npair_of(n), d.s_part + tr.tile, d.ntile);
+    overlap_partial<T, NO>(acc, n, d.s_part + tr.tile, d.ntile);
 }
 
 // Overlap partials of the orbital state itself (collapsed scheme).
@@ -366,19 +127,13 @@ __global__ __launch_bounds__(BS) void k_overlap_psi(const InstDesc *__restrict__
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
+    const int n = orbitals<NO>(d);
     const int s = tr.tile * BS + threadIdx.x;
     const T *psi = (const T *)d.psi;
-    double a[NO];
+    T a[NO];
 #pragma unroll
-    for (int j = 0; j < NO; ++j) a[j] = (s < d.nsite && j < n) ? (double)psi[(size_t)j * d.nsite + s] : 0.0;
-    double prod[NO * (NO + 1) / 2];
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < NO; ++j)
-#pragma unroll
-        for (int k = 0; k <= j; ++k) prod[q++] = a[j] * a[k];
-    block_sum_store(prod, npair_of(n), d.s_part + tr.tile, d.ntile);
+    for (int j = 0; j < NO; ++j) a[j] = (s < d.nsite && j < n) ? psi[(size_t)j * d.nsite + s] : (T)0;
+    overlap_partial<T, NO>(a, n, d.s_part + tr.tile, d.ntile);
 }
 
 // ---------------------------------------------------------- overlap / GS
@@ -455,7 +210,7 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
+    const int n = orbitals<NO>(d);
     const int s = tr.tile * BS + threadIdx.x;
     double m[NMOM];
 #pragma unroll
@@ -669,155 +424,6 @@ __global__ __launch_bounds__(BS) void k_vext(const InstDesc *__restrict__ descs,
     d.vext[s] = v;
 }
 
-// --------------------------------------------------------- stream-collide
-
-// Pull form of the lattice Boltzmann equation with the orthogonalisation and
-// potential sources: the population entering node r along v_p is the
-// post-collision population of r - v_p,
-//   f_jp(r; t+1) = (1 - omega) g_jp + omega xi_p psi*_j - dt chi_p V psi_hat_j  at r - v_p,
-// g_jp = sum_{l<=j} f_lp C_lj, and zero when r - v_p is outside the box.  The new
-// moment psi_j = sum_p f_jp and the overlap partials psi_j psi_k are fused.
-template <typename T, int NO, bool W>
-__global__ __launch_bounds__(BS) void k_stream_collide(const InstDesc *__restrict__ descs,
-                                                       const int2 *__restrict__ tiles, int parity)
-{
-    const TileRef tr = resolve(tiles);
-    const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
-    const int nx = d.nx, ny = d.ny, nz = d.nz;
-    const int s = tr.tile * BS + threadIdx.x;
-    const bool valid = s < d.nsite;
-    T acc[NO];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) acc[j] = (T)0;
-    if (valid) {
-        const size_t N = (size_t)d.nsite;
-        const T *__restrict__ fs = (const T *)(parity ? d.f1 : d.f0);
-        T *__restrict__ fd = (T *)(parity ? d.f0 : d.f1);
-        const T *__restrict__ ph = (const T *)d.psihat;
-        const T *__restrict__ pst = (const T *)d.psistar;
-        const T *__restrict__ Vp = (const T *)d.V;
-        const T a = (T)(1.0 - d.omega);
-        const T om = (T)d.omega;
-        const T dt = (T)d.dt;
-        T c[NO][NO];
-#pragma unroll
-        for (int l = 0; l < NO; ++l)
-#pragma unroll
-            for (int j = 0; j < NO; ++j) c[l][j] = (T)d.C[l * MAXO + j];
-        const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-            const int vx = VX(p), vy = VY(p), vz = VZ(p);
-            const bool ok = (unsigned)(x - vx) < (unsigned)nx && (unsigned)(y - vy) < (unsigned)ny &&
-                            (unsigned)(z - vz) < (unsigned)nz;
-            T out[NO];
-            if (ok) {
-                const int src = s - (vx + nx * (vy + ny * vz));
-                T fl[NO];
-#pragma unroll
-                for (int l = 0; l < NO; ++l)
-                    fl[l] = (l < n) ? __builtin_nontemporal_load(fs + ((size_t)l * Q + p) * N + src) : (T)0;
-                const T vn = Vp[src];
-                const T cp = om * (T)d.xi[p];
-                const T dp = dt * (T)d.chi[p] * vn;
-#pragma unroll
-                for (int j = 0; j < NO; ++j) {
-                    if (j < n) {
-                        T g;
-                        if (W) {
-                            g = c[j][j] * fl[j];
-                            out[j] = a * g + cp * pst[(size_t)j * N + src] - dp * ph[(size_t)j * N + src];
-                        } else {
-                            g = (T)0;
-#pragma unroll
-                            for (int l = 0; l <= j; ++l) g += c[l][j] * fl[l];
-                            out[j] = a * g + (cp - dp) * ph[(size_t)j * N + src];
-                        }
-                    } else {
-                        out[j] = (T)0;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < NO; ++j) out[j] = (T)0;
-            }
-#pragma unroll
-            for (int j = 0; j < NO; ++j) {
-                if (j < n) {
-                    // populations are read once per step: stream them past the caches
-                    __builtin_nontemporal_store(out[j], fd + ((size_t)j * Q + p) * N + s);
-                    acc[j] += out[j];
-                }
-            }
-        }
-        T *psi = (T *)d.psi;
-#pragma unroll
-        for (int j = 0; j < NO; ++j)
-            if (j < n) psi[(size_t)j * N + s] = acc[j];
-    }
-    double prod[NO * (NO + 1) / 2];
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < NO; ++j)
-#pragma unroll
-        for (int k = 0; k <= j; ++k) prod[q++] = (double)acc[j] * (double)acc[k];
-    block_sum_store(prod, npair_of(n), d.s_part + tr.tile, d.ntile);
-}
-
-// omega = 1 without populations: psi_j(r) <- sum_p [xi_p psi*_j - dt chi_p V psi_hat_j](r - v_p),
-// exactly the moment of the population update at omega = 1.
-template <typename T, int NO, bool W>
-__global__ __launch_bounds__(BS) void k_collapsed(const InstDesc *__restrict__ descs,
-                                                  const int2 *__restrict__ tiles)
-{
-    const TileRef tr = resolve(tiles);
-    const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
-    const int nx = d.nx, ny = d.ny, nz = d.nz;
-    const int s = tr.tile * BS + threadIdx.x;
-    const bool valid = s < d.nsite;
-    T acc[NO];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) acc[j] = (T)0;
-    if (valid) {
-        const size_t N = (size_t)d.nsite;
-        const T *__restrict__ ph = (const T *)d.psihat;
-        const T *__restrict__ pst = (const T *)d.psistar;
-        const T *__restrict__ Vp = (const T *)d.V;
-        const T dt = (T)d.dt;
-        const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
-#pragma unroll
-        for (int p = 0; p < Q; ++p) {
-            const int vx = VX(p), vy = VY(p), vz = VZ(p);
-            const bool ok = (unsigned)(x - vx) < (unsigned)nx && (unsigned)(y - vy) < (unsigned)ny &&
-                            (unsigned)(z - vz) < (unsigned)nz;
-            if (ok) {
-                const int src = s - (vx + nx * (vy + ny * vz));
-                const T cp = (T)d.xi[p];
-                const T dp = dt * (T)d.chi[p] * Vp[src];
-#pragma unroll
-                for (int j = 0; j < NO; ++j) {
-                    if (j < n) {
-                        if (W) acc[j] += cp * pst[(size_t)j * N + src] - dp * ph[(size_t)j * N + src];
-                        else acc[j] += (cp - dp) * ph[(size_t)j * N + src];
-                    }
-                }
-            }
-        }
-        T *psi = (T *)d.psi;
-#pragma unroll
-        for (int j = 0; j < NO; ++j)
-            if (j < n) psi[(size_t)j * N + s] = acc[j];
-    }
-    double prod[NO * (NO + 1) / 2];
-    int q = 0;
-#pragma unroll
-    for (int j = 0; j < NO; ++j)
-#pragma unroll
-        for (int k = 0; k <= j; ++k) prod[q++] = (double)acc[j] * (double)acc[k];
-    block_sum_store(prod, npair_of(n), d.s_part + tr.tile, d.ntile);
-}
 
 // ---------------------------------------------------------------- energies
 
@@ -829,7 +435,7 @@ __global__ __launch_bounds__(BS) void k_energy_terms(const InstDesc *__restrict_
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
-    const int n = d.n_orb;
+    const int n = orbitals<NO>(d);
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int s = tr.tile * BS + threadIdx.x;
     double v[2 * NO + NEBASE];
@@ -1066,23 +672,7 @@ int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st)
     });
 }
 
-int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
-{
-    return dispatch_tnw(pl, [&](auto tg) {
-        using TG = decltype(tg);
-        k_stream_collide<typename TG::T, TG::NO, TG::W><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, parity);
-        LAUNCH_CHECK();
-    });
-}
 
-int launch_collapsed_update(const Plan &pl, hipStream_t st)
-{
-    return dispatch_tnw(pl, [&](auto tg) {
-        using TG = decltype(tg);
-        k_collapsed<typename TG::T, TG::NO, TG::W><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
-        LAUNCH_CHECK();
-    });
-}
 
 int launch_energy_terms(const Plan &pl, hipStream_t st)
 {

@@ -78,6 +78,9 @@ SIGNATURES = {
     "lbks_set_timing": (c_int32, [c_void_p, c_int32]),
     "lbks_kernel_time": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int64)]),
     "lbks_copy_kernel": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "lbks_set_variant": (c_int32, [c_void_p, c_int32]),
+    "lbks_get_variant": (c_int32, [c_void_p]),
+    "lbks_autotune": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_double)]),
     "lbks_batch_create": (c_int32, [POINTER(lbks_device), POINTER(c_void_p)]),
     "lbks_batch_attach": (c_int32, [c_void_p, c_void_p]),
     "lbks_batch_detach": (c_int32, [c_void_p, c_void_p]),
@@ -285,6 +288,21 @@ class Solver:
 
     def set_timing(self, on: bool):
         _check(self.ctx, load().lbks_set_timing(self.ctx, 1 if on else 0))
+
+    def set_variant(self, v: int):
+        _check(self.ctx, load().lbks_set_variant(self.ctx, int(v)))
+
+    def variant(self) -> int:
+        return load().lbks_get_variant(self.ctx)
+
+    def autotune(self, reps: int = 5, force: bool = False):
+        """Pick the fastest update-kernel variant on the current state; returns
+        (variant, per-variant ms or None when the process cache answered)."""
+        ch = c_int32()
+        ms = (c_double * 4)()
+        _check(self.ctx, load().lbks_autotune(self.ctx, int(reps), 1 if force else 0, ctypes.byref(ch), ms))
+        times = list(ms)
+        return ch.value, (None if times[0] < 0 else times)
 
     def kernel_time(self):
         ms = c_double()

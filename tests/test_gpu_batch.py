@@ -37,8 +37,10 @@ def mixed_systems():
     ]
 
 
-def alone(L, system, kw, steps, tol=0.0, every=10):
+def alone(L, system, kw, steps, tol=0.0, every=10, variant=None):
     s = L.Solver.for_system(system, **kw)
+    if variant is not None:
+        s.set_variant(variant)
     out = s.relax(steps, dE_tol=tol, check_every=every)
     psi, rho = s.orbitals()
     e = s.energy()
@@ -51,12 +53,15 @@ def test_batch_equals_alone_fixed_steps(L):
     systems = mixed_systems()
     b = L.Batch()
     members = [b.add_system(sy, **kw) for sy, kw in systems]
+    variants = [0, 1, 2, 3, 3, 2]
+    for m, v in zip(members, variants):
+        m.set_variant(v)
     st, steps = b.relax(25, dE_tol=0.0, check_every=10)
     assert steps == [25] * len(systems)
     assert all(x == L.LBKS_NOT_CONVERGED for x in st)
-    for (sy, kw), s in zip(systems, members):
+    for (sy, kw), s, v in zip(systems, members, variants):
         psi, rho = s.orbitals()
-        _, psi_a, rho_a, _ = alone(L, sy, kw, 25)
+        _, psi_a, rho_a, _ = alone(L, sy, kw, 25, variant=v)
         assert np.array_equal(psi, psi_a) and np.array_equal(rho, rho_a), sy.name
     # members stay usable one by one, and continue in the batch
     e0 = members[0].energy()

@@ -214,3 +214,53 @@ def test_full_size_ne_fp64_two_steps(L):
     o.step()
     compare_state(s, o, 1e-11, 1e-11)
     s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update_kernel_variants_match_oracle(L, variant, prec):
+    """Every autotuner variant of the update kernels computes the same step."""
+    system = I.ne_atom().scaled(20)
+    say("variant", variant, "precision", prec)
+    s, o = make_pair(L, system, precision=prec)
+    s.set_variant(variant)
+    assert s.variant() == variant
+    s.relax(20)
+    for _ in range(20):
+        o.step()
+    if prec == 0:
+        compare_state(s, o, 1e-10, 1e-10)
+    else:
+        _, rho = s.orbitals()
+        _, rho_o = o.state()
+        assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-5 * np.linalg.norm(rho_o)
+    s.close()
+
+
+def test_autotune_leaves_the_trajectory_unchanged(L):
+    system = I.ne_atom().scaled(20)
+    say("autotune")
+    s, o = make_pair(L, system)
+    s.relax(5)
+    for _ in range(5):
+        o.step()
+    v, times = s.autotune(reps=3, force=True)
+    assert 0 <= v < 4 and times is not None and all(t > 0 for t in times)
+    assert s.variant() == v
+    v2, times2 = s.autotune(reps=3, force=False)       # cached
+    assert v2 == v and times2 is None
+    s.relax(15)
+    for _ in range(15):
+        o.step()
+    compare_state(s, o, 1e-10, 1e-10)
+    s.close()
+    c, oc = make_pair(L, system, scheme=L.LBKS_SCHEME_COLLAPSED)
+    c.relax(5)
+    for _ in range(5):
+        oc.step()
+    c.autotune(reps=2, force=True)
+    c.relax(5)
+    for _ in range(5):
+        oc.step()
+    compare_state(c, oc, 1e-10, 1e-10)
+    c.close()
