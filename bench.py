@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+I_SERVE_GRIDS = (48, 64, 80, 96, 112, 128)
 
 
 def workload(name):
@@ -42,6 +43,22 @@ def k1_bytes_per_launch(n_orb, nsite, s, scheme):
     if scheme == 0:
         return nsite * (n_orb * (2 * 19 * s + 2 * s) + s)
     return nsite * (n_orb * 2 * s + s)
+
+
+def measured_traffic(key):
+    """HBM bytes per stream-collide launch from the committed counter runs, or None
+    when the kernel sources changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for p in d["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    if h.hexdigest() != d["kernel_sha256"]:
+        return None
+    return d.get(key)
 
 
 def cpu_baseline(system, steps, threads):
@@ -84,6 +101,47 @@ def copy_calibration(nbytes, iters):
             "GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": 2 * nbytes / (ms * 1e-3) / 8e12}
 
 
+def h2o_batch_run(count, dE_tol, check_every, max_steps):
+    """64 H2O molecules (uneven grids) in one batch, FP32 bulk, until every one has
+    |dE| < dE_tol per check_every steps.  Returns the timing summary."""
+    import torch
+    from paper_1507_07666_amd import inputs as I
+    from paper_1507_07666_amd import lbks
+    systems = I.h2o_batch(count)
+    b = lbks.Batch()
+    members = [b.add_system(sy, precision=lbks.LBKS_FP32_BULK) for sy in systems]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, steps = b.relax(max_steps, dE_tol, check_every)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd = sum(sy.n_orb * sy.n_sites * k for sy, k in zip(systems, steps))
+    e = [m.energy()["e_total"] for m in members[:4]]
+    b.close()
+    return {"workload": f"{count} H2O, grids {{64,80,96,112}}^3 at 0.2 bohr, 5 orbitals, FP32 bulk, "
+                        f"|dE| < {dE_tol:g} Ha per {check_every} steps",
+            "solves": count, "converged": sum(1 for x in st if x == lbks.LBKS_OK),
+            "wall_s": wall, "h2o_solves_per_s": count / wall, "orbital_site_updates_per_s": upd / wall,
+            "steps_min": min(steps), "steps_max": max(steps), "nodes_total": sum(sy.n_sites for sy in systems),
+            "e_total_first4": e}
+
+
+def serve_run(n_requests, rate, check_every, dE_tol, budget_gb, grids):
+    from paper_1507_07666_amd import inputs as I
+    from paper_1507_07666_amd import serve
+    reqs = I.serving_stream(n_requests, rate=rate, seed=50, grids=grids)
+    cfg = serve.ServeConfig(hbm_budget=int(budget_gb * (1 << 30)), check_every=check_every, dE_tol=dE_tol)
+    srv = serve.Server(cfg)
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    srv.close()
+    out = serve.summarize(res, wall)
+    out.update({"rate_per_s": rate, "budget_gb": budget_gb, "peak_slots": srv.peak_active,
+                "peak_bytes": srv.peak_used, "grids": list(grids)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +155,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default update-kernel variant")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--rate", type=float, default=2.0, help="serving arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: time the library's plain copy kernel (bandwidth calibration)")
     ap.add_argument("--copy-mib", type=int, default=678, help="bytes read (= written) by one copy launch")
@@ -113,6 +175,12 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.copy_mib << 20, max(args.steps, 10))), flush=True)
+        return
+    if args.workload == "h2o_batch":
+        print(json.dumps(h2o_batch_run(args.batch_count, 1e-7, 100, 20000)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(serve_run(args.requests, args.rate, 100, 1e-7, args.budget_gb, I_SERVE_GRIDS)), flush=True)
         return
     system = workload(args.workload)
     prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
@@ -161,8 +229,9 @@ def main():
         avg_s = k1_ms / k1_n * 1e-3
         alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme)
         ach = alg / avg_s / 1e9
+        tkey = f"{args.workload}_{args.precision}_v{variant}" if scheme == 0 else None
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                           "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(tkey) if tkey else None,
                            "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed",
                            "avg_us": avg_s * 1e6, "launches": k1_n, "alg_bytes_per_launch": alg}
     if not args.no_cpu_baseline:
