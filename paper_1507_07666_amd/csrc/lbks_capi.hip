@@ -269,8 +269,10 @@ int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
         PCHK(launch_ghost(pl, st));
         for (int k = 0; k < sweeps; ++k) {
             PCHK(launch_sor(pl, 0, st));
-            PCHK(launch_sor(pl, 1, st));
+            if (k + 1 < sweeps) PCHK(launch_sor(pl, 1, st));
         }
+        // the last black half-sweep also evaluates the potential
+        if (sweeps > 0) return launch_sor_black_potential(pl, st);
     }
     PCHK(launch_potential(pl, 0, st));
     return 0;

@@ -102,6 +102,7 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st);
 int launch_multipole_finalize(const Plan &pl, hipStream_t st);
 int launch_ghost(const Plan &pl, hipStream_t st);
 int launch_sor(const Plan &pl, int color, hipStream_t st);
+int launch_sor_black_potential(const Plan &pl, hipStream_t st);   // last black half-sweep + V
 int launch_potential(const Plan &pl, int to_fp64, hipStream_t st);
 int launch_stream_collide(const Plan &pl, int parity, hipStream_t st);
 int launch_collapsed_update(const Plan &pl, hipStream_t st);

@@ -378,8 +378,23 @@ __global__ __launch_bounds__(FB) void k_residual_finalize(const InstDesc *__rest
 
 // ------------------------------------------------------------- potential
 
-// V = V_ext + V_H + v_x + v_c at every node (FP64 arithmetic; stored in the bulk
-// precision for the collide, or in FP64 for the energies).
+// V = V_ext + V_H + v_x + v_c at node s = (x, y, z), summed in that order in FP64.
+template <typename T>
+__device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, int y, int z)
+{
+    double V = d.vext[s];
+    if (d.hartree) V += d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)];
+    if (d.xc) {
+        double ex, ec, vx, vc;
+        xc_eval(d.xc, (double)((const T *)d.rho)[s], d.rho_floor, ex, ec, vx, vc);
+        V += vx;
+        V += vc;
+    }
+    return V;
+}
+
+// The KS potential at every node (stored in the bulk precision for the collide,
+// or in FP64 for the energies).
 template <typename T>
 __global__ __launch_bounds__(BS) void k_potential(const InstDesc *__restrict__ descs,
                                                   const int2 *__restrict__ tiles, int to_fp64)
@@ -388,20 +403,44 @@ __global__ __launch_bounds__(BS) void k_potential(const InstDesc *__restrict__ d
     const InstDesc &d = descs[tr.inst];
     const int s = tr.tile * BS + threadIdx.x;
     if (s >= d.nsite) return;
-    double V = d.vext[s];
-    if (d.hartree) {
-        const int nx = d.nx, ny = d.ny;
-        const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
-        V += d.vh[((size_t)(z + 1) * (ny + 2) + (y + 1)) * (nx + 2) + (x + 1)];
-    }
-    if (d.xc) {
-        double ex, ec, vx, vc;
-        xc_eval(d.xc, (double)((const T *)d.rho)[s], d.rho_floor, ex, ec, vx, vc);
-        V += vx;
-        V += vc;
-    }
+    const int x = s % d.nx, yz = s / d.nx, y = yz % d.ny, z = yz / d.ny;
+    const double V = potential_at<T>(d, s, x, y, z);
     if (to_fp64) d.Vd[s] = V;
     else ((T *)d.V)[s] = (T)V;
+}
+
+// Last half-sweep of a step fused with the potential: each thread owns one x-pair
+// (one red and one black node), relaxes the black node, and then writes V at both
+// nodes (the red one is final since the preceding red half-sweep).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_sor_black_potential(const InstDesc *__restrict__ descs,
+                                                            const int2 *__restrict__ tiles)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int hx = (nx + 1) >> 1;
+    const int t = tr.tile * BS + threadIdx.x;
+    if (t >= hx * ny * nz) return;
+    const int xh = t % hx, yz = t / hx, y = yz % ny, z = yz / ny;
+    const int xb = 2 * xh + ((y + z + 1) & 1);
+    const int xr = 2 * xh + ((y + z) & 1);
+    if (xb < nx) {
+        const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
+        const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(xb + 1);
+        double *vh = d.vh;
+        const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
+        const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
+        const double rho = (double)((const T *)d.rho)[((size_t)z * ny + y) * nx + xb];
+        const double gs = (nb + four_pi_h2 * rho) / 6.0;
+        vh[idx] = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
+        const int sb = (z * ny + y) * nx + xb;
+        ((T *)d.V)[sb] = (T)potential_at<T>(d, sb, xb, y, z);
+    }
+    if (xr < nx) {
+        const int sr = (z * ny + y) * nx + xr;
+        ((T *)d.V)[sr] = (T)potential_at<T>(d, sr, xr, y, z);
+    }
 }
 
 // V_ext(r) = -sum_I Z_I / sqrt(|r - R_I|^2 + a^2); ZR = [Z, x, y, z] per nucleus, then a^2.
@@ -635,6 +674,15 @@ int launch_sor(const Plan &pl, int color, hipStream_t st)
     return dispatch_tt(pl, [&](auto tg) {
         using TG = decltype(tg);
         k_sor<typename TG::T><<<grid_sor(pl), BS, 0, st>>>(pl.d_desc, pl.tt.sor, color);
+        LAUNCH_CHECK();
+    });
+}
+
+int launch_sor_black_potential(const Plan &pl, hipStream_t st)
+{
+    return dispatch_tt(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_sor_black_potential<typename TG::T><<<grid_sor(pl), BS, 0, st>>>(pl.d_desc, pl.tt.sor);
         LAUNCH_CHECK();
     });
 }
