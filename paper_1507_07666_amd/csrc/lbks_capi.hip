@@ -137,7 +137,7 @@ void lattice_constants(double D, double *xi, double *chi)
 }
 
 struct Layout {
-    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, C,
+    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, g_part, C,
         scal, stage, zr;
     size_t total = 0;
 };
@@ -210,6 +210,10 @@ Layout plan_layout(const lbks_params *p)
     take(L.m_part, (size_t)padded_cols(NMOM) * ntile * 8);
     take(L.e_part, (size_t)padded_cols(2 * no + NEBASE) * ntile * 8);
     take(L.r_part, (size_t)padded_cols(2) * ntile * 8);
+    {
+        const int widest = std::max(std::max(no * (no + 1) / 2, NMOM), 2 * no + NEBASE);
+        take(L.g_part, (size_t)padded_cols(widest) * RG * 8);
+    }
     take(L.C, 2 * MAXO * MAXO * 8);
     take(L.scal, SC_SIZE * 8);
     take(L.stage, (n + 1) * N * 8);
@@ -516,6 +520,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     h.m_part = (double *)at(L.m_part);
     h.e_part = (double *)at(L.e_part);
     h.r_part = (double *)at(L.r_part);
+    h.g_part = (double *)at(L.g_part);
     h.C = (double *)at(L.C);
     h.scal = (double *)at(L.scal);
     h.stage = (double *)at(L.stage);

@@ -58,29 +58,64 @@ __device__ __forceinline__ TileRef resolve(const int2 *table)
     return {0, b};
 }
 
-__device__ __forceinline__ int resolve_inst(const int *list)
+__host__ __device__ constexpr int pow2_ceil(int n) { return n <= 1 ? 1 : 2 * pow2_ceil((n + 1) / 2); }
+__host__ __device__ constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+// One halving step of wave_reduce_scatter: lanes whose bit M is set keep the
+// upper half of their W remaining elements, the others the lower half, and each
+// adds the partner's (lane ^ M) copy of the half it keeps.
+template <int W, int M, int P>
+__device__ __forceinline__ void halve_step(double (&v)[P], int lane)
 {
-    return list ? list[blockIdx.x] : (int)blockIdx.x;
+    if constexpr (W > 1) {
+        const bool hi = (lane & M) != 0;
+#pragma unroll
+        for (int k = 0; k < W / 2; ++k) {
+            const double keep = hi ? v[k + W / 2] : v[k];
+            const double give = hi ? v[k] : v[k + W / 2];
+            v[k] = keep + __shfl_xor(give, M, 64);
+        }
+        halve_step<W / 2, M / 2, P>(v, lane);
+    }
 }
 
-__device__ __forceinline__ double wave_sum(double x)
+// Element-wise sum of v[0..P) over the 64 lanes of a wave (P a power of two, at
+// most 64) by recursive halving: log2 P exchange steps leave each lane one element
+// summed over 64 / P lanes, which a butterfly over the remaining lane bits
+// completes.  P - 1 + log2(64 / P) shuffles in all, against 6 P for a butterfly
+// per element.  Lane l returns the total of element (l >> (6 - log2 P)) & (P - 1);
+// the order of the additions is fixed.  v is overwritten.
+template <int P>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[P])
 {
+    static_assert(P >= 1 && P <= 64 && (P & (P - 1)) == 0, "P must be a power of two <= 64");
+    const int lane = threadIdx.x & 63;
+    halve_step<P, 32, P>(v, lane);
+    double x = v[0];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    for (int m = 32 / P; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
     return x;
 }
 
 // Sum v[0..nv) over the workgroup; thread q < nv writes its total to out[q * stride].
+// The wave sums go by chunks of up to 16 elements through wave_reduce_scatter,
+// then the waves are added in order.
 template <int NV>
-__device__ __forceinline__ void block_sum_store(double (&v)[NV], int nv, double *out, int stride)
+__device__ __forceinline__ void block_sum_store(const double (&v)[NV], int nv, double *out, int stride)
 {
-    __shared__ double red[BS / 64][NV];
+    constexpr int C = pow2_ceil(NV < 16 ? NV : 16);   // elements per reduce-scatter
+    constexpr int NCH = (NV + C - 1) / C;
+    constexpr int SH = 6 - ilog2(C);                   // lane l holds element l >> SH of its chunk
+    __shared__ double red[BS / 64][NCH * C];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            const double x = wave_sum(v[q]);
-            if (lane == 0) red[wave][q] = x;
+    for (int c = 0; c < NCH; ++c) {
+        if (c * C < nv) {
+            double t[C];
+#pragma unroll
+            for (int e = 0; e < C; ++e) t[e] = (c * C + e < NV) ? v[c * C + e] : 0.0;
+            const double x = wave_reduce_scatter<C>(t);
+            if ((lane & ((1 << SH) - 1)) == 0) red[wave][c * C + (lane >> SH)] = x;
         }
     }
     __syncthreads();
@@ -92,52 +127,93 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], int nv, double 
     }
 }
 
-constexpr int FB = 1024;   // threads of the per-instance finalize kernels
+// Grid of a finalize kernel: RG workgroups per instance.  Workgroup b serves
+// instance list[b / RG] and takes group g of its tiles; g runs over the XCD of b
+// in contiguous blocks, as the site kernels' tiles do.
+struct GroupRef {
+    int inst, g;
+};
 
-// Column sums out[q] = sum_t part[q * ntile + t] for q < nq, in a fixed order
-// (each thread strides the tiles, then the waves are summed in order).  The
-// partial arrays hold whole chunks of RCH columns (unused ones stay zero), so
-// every load is unconditional and all of a thread's loads are in flight at once.
-// `out` is LDS; every thread of the FB-wide workgroup must call this.
-static __device__ void reduce_columns(const double *__restrict__ part, int ntile, int nq, double *out)
+__device__ __forceinline__ GroupRef resolve_group(const int *list)
 {
-    constexpr int U = 4;   // tiles per thread per round
-    __shared__ double red[FB / 64][RCH];
+    const int b = (int)blockIdx.x;
+    return {list ? list[b / RG] : b / RG, xcd_remap(b % RG, RG)};
+}
+
+// A global-memory view of a device pointer (loads become global_load, not flat).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+// acc[c] += col[c * ntile + t] for c < NC and t = t0 + tid, t0 + tid + BS, ... < t1;
+// the NC loads of a round are unconditional and in flight together.
+template <int NC>
+__device__ __forceinline__ void sum_tiles(const double *col, int ntile, int t0, int t1, double (&acc)[2 * RCH])
+{
+    const auto *g = gmem(col);
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += BS) {
+        double v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = g[(size_t)c * ntile + t];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] += v[c];
+    }
+}
+
+// Column totals out[q] = sum_t part[q * ntile + t] (q < nq) of one instance's tile
+// partials, in two levels within one launch of RG workgroups per instance.
+// Workgroup g adds tiles [g ntile / RG, (g + 1) ntile / RG) of every column and
+// stores the sums at g_part[q * RG + g]; the workgroup that finishes last (a
+// device-scope counter, reset by that workgroup) adds the RG sums of each column
+// in the order g = 0, 1, ..., leaves the totals in `out` (LDS) and returns true;
+// the others return false.  Every addition is in a fixed order, so the totals do
+// not depend on which workgroup finishes last.  No workgroup waits for another.
+// The partial arrays hold whole chunks of RCH columns (unused ones stay zero).
+// Every thread of the BS-wide workgroup must call this.
+static __device__ bool reduce_columns(const double *__restrict__ part, int ntile, int nq, double *g_part,
+                                      unsigned *count, int g, double *out)
+{
+    __shared__ double red[BS / 64][2 * RCH];
+    __shared__ int last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int q0 = 0; q0 < nq; q0 += RCH) {
+    const int t0 = (int)((long long)ntile * g / RG), t1 = (int)((long long)ntile * (g + 1) / RG);
+    const int ncol = padded_cols(nq);
+    for (int q0 = 0; q0 < ncol; q0 += 2 * RCH) {
+        const int nc = ncol - q0 < 2 * RCH ? ncol - q0 : 2 * RCH;   // RCH or 2 RCH
         const double *col = part + (size_t)q0 * ntile;
-        double acc[RCH];
+        double acc[2 * RCH];
 #pragma unroll
-        for (int c = 0; c < RCH; ++c) acc[c] = 0.0;
-        for (int t0 = 0; t0 < ntile; t0 += U * FB) {
-            double v[U][RCH];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int t = t0 + k * FB + (int)threadIdx.x;
-                const int tc = t < ntile ? t : ntile - 1;
-#pragma unroll
-                for (int c = 0; c < RCH; ++c) v[k][c] = col[(size_t)c * ntile + tc];
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const double w = (t0 + k * FB + (int)threadIdx.x) < ntile ? 1.0 : 0.0;
-#pragma unroll
-                for (int c = 0; c < RCH; ++c) acc[c] += w * v[k][c];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < RCH; ++c) {
-            const double x = wave_sum(acc[c]);
-            if (lane == 0) red[wave][c] = x;
-        }
+        for (int c = 0; c < 2 * RCH; ++c) acc[c] = 0.0;
+        if (nc == 2 * RCH) sum_tiles<2 * RCH>(col, ntile, t0, t1, acc);
+        else sum_tiles<RCH>(col, ntile, t0, t1, acc);
+        const double x = wave_reduce_scatter<2 * RCH>(acc);
+        if ((lane & 3) == 0) red[wave][lane >> 2] = x;
         __syncthreads();
-        if ((int)threadIdx.x < RCH && q0 + (int)threadIdx.x < nq) {
-            double sum = 0.0;
-            for (int w = 0; w < FB / 64; ++w) sum += red[w][threadIdx.x];
-            out[q0 + threadIdx.x] = sum;
+        if ((int)threadIdx.x < nc) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS / 64; ++w) s += red[w][threadIdx.x];
+            g_part[(size_t)(q0 + threadIdx.x) * RG + g] = s;
         }
         __syncthreads();
     }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(count, 1u) == (unsigned)(RG - 1);
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    if ((int)threadIdx.x < nq) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < RG; ++k) s += g_part[(size_t)threadIdx.x * RG + k];
+        out[threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0) atomicExch(count, 0u);
+    __syncthreads();
+    return true;
 }
 
 __device__ __forceinline__ double node_coord(int i, int n, double h)
@@ -353,6 +429,7 @@ static inline int grid_site(const Plan &pl) { return pl.tt.site ? pl.tt.n_site :
 static inline int grid_ghost(const Plan &pl) { return pl.tt.ghost ? pl.tt.n_ghost : pl.ntile_ghost; }
 static inline int grid_sor(const Plan &pl) { return pl.tt.sor ? pl.tt.n_sor : pl.ntile_sor; }
 static inline int grid_inst(const Plan &pl) { return pl.tt.inst ? pl.tt.n_inst : 1; }
+static inline int grid_group(const Plan &pl) { return RG * grid_inst(pl); }
 
 #define LAUNCH_CHECK() return (int)hipGetLastError()
 

@@ -20,6 +20,8 @@ constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
 
+constexpr int RG = 32;         // first-level workgroups per instance of the finalize kernels
+
 // Columns of a partial array padded to a whole number of chunks.
 __host__ __device__ constexpr int padded_cols(int nq) { return (nq + RCH - 1) / RCH * RCH; }
 
@@ -29,6 +31,7 @@ constexpr int SC_S = 16;                   // packed lower overlap, 136 values
 constexpr int SC_ENER = 160;               // lbks_energies prefix: 9 + 16 doubles
 constexpr int SC_RES = 192;                // Poisson relative residual
 constexpr int SC_ERR = 193;                // nonzero: overlap not finite / not SPD
+constexpr int SC_CNT = 194;                // finalize-kernel counter (an unsigned in this slot)
 constexpr int SC_SIZE = 200;
 
 struct InstDesc {
@@ -56,6 +59,7 @@ struct InstDesc {
     double *m_part;            // [padded_cols(NMOM)][ntile]
     double *e_part;            // [padded_cols(2*bucket(n_orb) + NEBASE)][ntile]
     double *r_part;            // [padded_cols(2)][ntile]
+    double *g_part;            // [padded_cols(widest partial)][RG] first-level column sums
     double *C;                 // [MAXO*MAXO] C, then [MAXO*MAXO] C* (W mode)
     double *scal;              // [SC_SIZE]
     double *stage;             // FP64 staging, (n_orb + 1) * nsite

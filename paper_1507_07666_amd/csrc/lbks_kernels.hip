@@ -142,64 +142,75 @@ __global__ __launch_bounds__(BS) void k_overlap_psi(const InstDesc *__restrict__
 // (psi_hat_j = sum_{l<=j} psi_l C_lj, classical Gram-Schmidt order).  W:
 // n_j = sqrt(S_jj), C = diag(1/n), C*_lj = -Lambda_jl / n_l (l < j), C*_jj = 1/n_j
 // with Lambda_jl = S_jl / (n_j n_l), i.e. psi*_j = psi_hat_j - sum_{l<j} Lambda_jl psi_hat_l.
-__global__ __launch_bounds__(FB) void k_overlap_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restrict__ descs,
                                                          const int *__restrict__ list)
 {
-    const InstDesc &d = descs[resolve_inst(list)];
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
     const int n = d.n_orb, np = npair_of(n);
     __shared__ double S[MAXO * (MAXO + 1) / 2];
     __shared__ double L[MAXO][MAXO + 1];
     __shared__ double Li[MAXO][MAXO + 1];
-    reduce_columns(d.s_part, d.ntile, np, S);
-    if (threadIdx.x != 0) return;
+    if (!reduce_columns(d.s_part, d.ntile, np, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, S)) return;
+    // the first wave finishes: lane i owns row i of L, lane c column c of L^{-1}
+    const int lane = threadIdx.x;
+    const bool w0 = threadIdx.x < 64;
     double *C = d.C;
     double *Cs = d.C + MAXO * MAXO;
     bool bad = false;
-    for (int q = 0; q < np; ++q) {
-        S[q] *= d.h3;
-        d.scal[SC_S + q] = S[q];
-        if (!isfinite(S[q])) bad = true;
-    }
+    if (w0)
+        for (int q = lane; q < np; q += 64) {
+            S[q] *= d.h3;
+            d.scal[SC_S + q] = S[q];
+            if (!isfinite(S[q])) bad = true;
+        }
+    __syncthreads();
     auto Sget = [&](int i, int j) { return i >= j ? S[i * (i + 1) / 2 + j] : S[j * (j + 1) / 2 + i]; };
     // entries outside the n x n block stay zero from creation
     if (d.ortho == 0) {
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j <= i; ++j) {
-                double sum = Sget(i, j);
-                for (int k = 0; k < j; ++k) sum -= L[i][k] * L[j][k];
-                if (i == j) {
-                    if (!(sum > 0.0)) {
-                        bad = true;
-                        sum = 1.0;
-                    }
-                    L[i][i] = sqrt(sum);
-                } else {
-                    L[i][j] = sum / L[j][j];
-                }
+        // Cholesky S = L L^T by columns: L_jj = sqrt(S_jj - sum_k<j L_jk^2),
+        // L_ij = (S_ij - sum_k<j L_ik L_jk) / L_jj for i > j
+        for (int j = 0; j < n; ++j) {
+            double sum = 0.0;
+            if (w0 && lane >= j && lane < n) {
+                sum = Sget(lane, j);
+                for (int k = 0; k < j; ++k) sum -= L[lane][k] * L[j][k];
             }
+            double djj = __shfl(sum, j, 64);
+            if (!(djj > 0.0)) {
+                if (w0) bad = true;
+                djj = 1.0;
+            }
+            const double ljj = sqrt(djj);
+            if (w0 && lane == j) L[j][j] = ljj;
+            else if (w0 && lane > j && lane < n) L[lane][j] = sum / ljj;
+            __syncthreads();
+        }
         // C = L^{-T}: column c of L^{-1} by forward substitution; C[l][j] = Linv[j][l]
-        for (int c = 0; c < n; ++c)
+        if (w0 && lane < n) {
+            const int c = lane;
             for (int i = c; i < n; ++i) {
                 double sum = (i == c) ? 1.0 : 0.0;
                 for (int k = c; k < i; ++k) sum -= L[i][k] * Li[k][c];
                 Li[i][c] = sum / L[i][i];
             }
-        for (int l = 0; l < n; ++l)
-            for (int j = l; j < n; ++j) C[l * MAXO + j] = Li[j][l];
-    } else {
-        double nrm[MAXO];
-        for (int j = 0; j < n; ++j) {
-            const double sjj = Sget(j, j);
-            if (!(sjj > 0.0)) bad = true;
-            nrm[j] = sqrt(sjj > 0.0 ? sjj : 1.0);
+            for (int j = c; j < n; ++j) C[c * MAXO + j] = Li[j][c];
         }
-        for (int j = 0; j < n; ++j) {
-            C[j * MAXO + j] = 1.0 / nrm[j];
-            Cs[j * MAXO + j] = 1.0 / nrm[j];
-            for (int l = 0; l < j; ++l) Cs[l * MAXO + j] = -(Sget(j, l) / (nrm[j] * nrm[l])) / nrm[l];
+    } else if (w0 && lane < n) {
+        const int j = lane;
+        const double sjj = Sget(j, j);
+        if (!(sjj > 0.0)) bad = true;
+        const double nj = sqrt(sjj > 0.0 ? sjj : 1.0);
+        C[j * MAXO + j] = 1.0 / nj;
+        Cs[j * MAXO + j] = 1.0 / nj;
+        for (int l = 0; l < j; ++l) {
+            const double sll = Sget(l, l);
+            const double nl = sqrt(sll > 0.0 ? sll : 1.0);
+            Cs[l * MAXO + j] = -(Sget(j, l) / (nj * nl)) / nl;
         }
     }
-    if (bad) d.scal[SC_ERR] = 1.0;
+    bad = __any(bad);
+    if (bad && lane == 0) d.scal[SC_ERR] = 1.0;   // lane 0 of the first wave: bad only ever set there
 }
 
 // psi_hat = psi C (psi* = psi C* in W mode), rho = sum_j occ_j psi_hat_j^2 and
@@ -266,12 +277,13 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 
 // ---------------------------------------------------------------- Hartree
 
-__global__ __launch_bounds__(FB) void k_multipole_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(BS) void k_multipole_finalize(const InstDesc *__restrict__ descs,
                                                            const int *__restrict__ list)
 {
-    const InstDesc &d = descs[resolve_inst(list)];
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
     __shared__ double m[NMOM];
-    reduce_columns(d.m_part, d.ntile, NMOM, m);
+    if (!reduce_columns(d.m_part, d.ntile, NMOM, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, m)) return;
     if ((int)threadIdx.x < NMOM) d.scal[SC_MOM + threadIdx.x] = m[threadIdx.x] * d.h3;
 }
 
@@ -367,12 +379,13 @@ __global__ __launch_bounds__(BS) void k_residual(const InstDesc *__restrict__ de
     block_sum_store(v, 2, d.r_part + tr.tile, d.ntile);
 }
 
-__global__ __launch_bounds__(FB) void k_residual_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(BS) void k_residual_finalize(const InstDesc *__restrict__ descs,
                                                           const int *__restrict__ list)
 {
-    const InstDesc &d = descs[resolve_inst(list)];
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
     __shared__ double acc[2];
-    reduce_columns(d.r_part, d.ntile, 2, acc);
+    if (!reduce_columns(d.r_part, d.ntile, 2, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, acc)) return;
     if (threadIdx.x == 0) d.scal[SC_RES] = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : sqrt(acc[0]);
 }
 
@@ -531,14 +544,15 @@ __global__ __launch_bounds__(BS) void k_energy_terms(const InstDesc *__restrict_
     block_sum_store(v, 2 * NO + NEBASE, d.e_part + tr.tile, d.ntile);
 }
 
-__global__ __launch_bounds__(FB) void k_energy_finalize(const InstDesc *__restrict__ descs,
+__global__ __launch_bounds__(BS) void k_energy_finalize(const InstDesc *__restrict__ descs,
                                                         const int *__restrict__ list)
 {
-    const InstDesc &d = descs[resolve_inst(list)];
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
     const int n = d.n_orb, no = d.n_orb <= 5 ? d.n_orb : (d.n_orb <= 8 ? 8 : 16);
     const int nv = 2 * no + NEBASE;
     __shared__ double tot[2 * MAXO + NEBASE];
-    reduce_columns(d.e_part, d.ntile, nv, tot);
+    if (!reduce_columns(d.e_part, d.ntile, nv, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, tot)) return;
     if (threadIdx.x == 0)
         for (int q = 0; q < nv; ++q) tot[q] *= d.h3;
     __syncthreads();
@@ -644,7 +658,7 @@ int launch_overlap_psi(const Plan &pl, hipStream_t st)
 
 int launch_overlap_finalize(const Plan &pl, hipStream_t st)
 {
-    k_overlap_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_overlap_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -659,7 +673,7 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st)
 
 int launch_multipole_finalize(const Plan &pl, hipStream_t st)
 {
-    k_multipole_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_multipole_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -698,7 +712,7 @@ int launch_residual(const Plan &pl, hipStream_t st)
 
 int launch_residual_finalize(const Plan &pl, hipStream_t st)
 {
-    k_residual_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_residual_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
@@ -733,7 +747,7 @@ int launch_energy_terms(const Plan &pl, hipStream_t st)
 
 int launch_energy_finalize(const Plan &pl, hipStream_t st)
 {
-    k_energy_finalize<<<grid_inst(pl), FB, 0, st>>>(pl.d_desc, pl.tt.inst);
+    k_energy_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
 
