@@ -358,6 +358,50 @@ double orc_enn(int nnuc, const double *Z, const double *R)
     return e;
 }
 
+/*
+ * Forces on the nuclei in the Born-Oppenheimer scenario (section "Concurrent
+ * Dynamics": the ions move on the surface defined by the electronic ground
+ * state).  Hellmann-Feynman: with the density held fixed, the electronic force
+ * is minus the derivative of <V_ext|rho> with respect to R_I,
+ *   F_I^el = Z_I h^3 sum_r rho(r) (r - R_I) / (|r - R_I|^2 + a^2)^(3/2),
+ * and the ion-ion force is minus the gradient of E_NN,
+ *   F_I^NN = sum_{J != I} Z_I Z_J (R_I - R_J) / |R_I - R_J|^3.
+ * F is [nnuc][3], electronic plus ion-ion, in hartree per bohr.  Sums run over
+ * the nodes in site order.
+ */
+void orc_forces(int nx, int ny, int nz, double h, int nnuc, const double *Z, const double *R,
+                double a, const double *rho, double *F)
+{
+    for (int I = 0; I < nnuc; ++I) {
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    double dx = coord(i, nx, h) - R[3 * I];
+                    double dy = coord(j, ny, h) - R[3 * I + 1];
+                    double dz = coord(k, nz, h) - R[3 * I + 2];
+                    double d2 = dx * dx + dy * dy + dz * dz + a * a;
+                    double w = rho[((i64)k * ny + j) * nx + i] / (d2 * sqrt(d2));
+                    fx += w * dx;
+                    fy += w * dy;
+                    fz += w * dz;
+                }
+        double hz = Z[I] * h * h * h;
+        F[3 * I] = hz * fx;
+        F[3 * I + 1] = hz * fy;
+        F[3 * I + 2] = hz * fz;
+        for (int J = 0; J < nnuc; ++J) {
+            if (J == I) continue;
+            double dx = R[3 * I] - R[3 * J], dy = R[3 * I + 1] - R[3 * J + 1], dz = R[3 * I + 2] - R[3 * J + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            double c = Z[I] * Z[J] / (r * r * r);
+            F[3 * I] += c * dx;
+            F[3 * I + 1] += c * dy;
+            F[3 * I + 2] += c * dz;
+        }
+    }
+}
+
 enum { ORC_XC_NONE = 0, ORC_XC_X = 1, ORC_XC_X_LYPLOCAL = 2, ORC_XC_X_PZ81 = 3 };
 
 /*

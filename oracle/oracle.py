@@ -77,6 +77,7 @@ def lib():
             "orc_vh_interior": (None, [I, I, I, P, P]),
             "orc_vext": (None, [I, I, I, D, I, P, P, D, P]),
             "orc_enn": (D, [I, P, P]),
+            "orc_forces": (None, [I, I, I, D, I, P, P, D, P, P]),
             "orc_xc": (None, [I, i64, P, D, P, P, P, P]),
             "orc_collide": (None, [I, i64, D, D, P, P, P, P, P, P, P]),
             "orc_stream": (None, [I, I, I, I, P, P, P]),
@@ -215,11 +216,13 @@ class Oracle:
         self.L.orc_vext(nx, ny, nz, self.prm.h, len(Z), _p(Z), _p(R), self.prm.softening,
                         _p(self.vext))
         self.e_nn = self.L.orc_enn(len(Z), _p(Z), _p(R))
+        self.nuclei = (Z.copy(), R.copy())
         self.e_prev = None
 
     def set_potential(self, vext):
         self.vext = np.ascontiguousarray(vext, dtype=np.float64).reshape(self.N).copy()
         self.e_nn = 0.0
+        self.nuclei = None
         self.e_prev = None
 
     def set_orbitals(self, psi0):
@@ -365,6 +368,21 @@ class Oracle:
         ne = h3 * self.L.orc_sum(self.N, _p(rho))
         et = e_kin + e_ext + e_h + e_x + e_c + self.e_nn
         return Energies(et, e_kin, e_ext, e_h, e_x, e_c, self.e_nn, ne, res, eps, self.steps)
+
+    def forces(self) -> np.ndarray:
+        """Hellmann-Feynman forces on the nuclei, [n][3] hartree/bohr, from the
+        density of the orthonormalised current orbitals (Born-Oppenheimer scenario
+        of the section on concurrent dynamics; orc_forces)."""
+        p = self.prm
+        psihat, _, _, _ = self.orthonormalise(self.moment(), with_g=False)
+        rho = np.ascontiguousarray(self.density(psihat))
+        if getattr(self, "nuclei", None) is None:
+            raise ValueError("forces need nuclei (set_nuclei)")
+        Z, R = self.nuclei
+        F = np.zeros((len(Z), 3))
+        nx, ny, nz = p.dims
+        self.L.orc_forces(nx, ny, nz, p.h, len(Z), _p(Z), _p(R), p.softening, _p(rho), _p(F))
+        return F
 
     def relax(self, max_steps, dE_tol=0.0, check_every=100, progress=None):
         """Run steps in chunks of check_every; after each chunk (only if dE_tol > 0)
