@@ -101,15 +101,19 @@ def copy_calibration(nbytes, iters):
             "GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": 2 * nbytes / (ms * 1e-3) / 8e12}
 
 
-def h2o_batch_run(count, dE_tol, check_every, max_steps):
-    """64 H2O molecules (uneven grids) in one batch, FP32 bulk, until every one has
-    |dE| < dE_tol per check_every steps.  Returns the timing summary."""
+def h2o_batch_run(count, check_every, max_steps):
+    """64 H2O molecules (uneven grids) in one batch, FP32 bulk, until every one meets
+    the FP32 stopping rule (energy within 2e-6 Ha and eigenvalue sum within 1e-6 Ha
+    on two consecutive checks).  Returns the timing summary."""
     import torch
     from paper_1507_07666_amd import inputs as I
     from paper_1507_07666_amd import lbks
+    from paper_1507_07666_amd.serve import FP32_RULE
+    dE_tol = FP32_RULE["dE_tol"]
     systems = I.h2o_batch(count)
     b = lbks.Batch()
-    members = [b.add_system(sy, precision=lbks.LBKS_FP32_BULK) for sy in systems]
+    members = [b.add_system(sy, precision=lbks.LBKS_FP32_BULK, deps_tol=FP32_RULE["deps_tol"],
+                            stop_checks=FP32_RULE["stop_checks"]) for sy in systems]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, steps = b.relax(max_steps, dE_tol, check_every)
@@ -119,18 +123,19 @@ def h2o_batch_run(count, dE_tol, check_every, max_steps):
     e = [m.energy()["e_total"] for m in members[:4]]
     b.close()
     return {"workload": f"{count} H2O, grids {{64,80,96,112}}^3 at 0.2 bohr, 5 orbitals, FP32 bulk, "
-                        f"|dE| < {dE_tol:g} Ha per {check_every} steps",
+                        f"|dE| < {dE_tol:g} Ha and |d sum eps| < {FP32_RULE['deps_tol']:g} Ha per {check_every} "
+                        f"steps on {FP32_RULE['stop_checks']} consecutive checks",
             "solves": count, "converged": sum(1 for x in st if x == lbks.LBKS_OK),
             "wall_s": wall, "h2o_solves_per_s": count / wall, "orbital_site_updates_per_s": upd / wall,
             "steps_min": min(steps), "steps_max": max(steps), "nodes_total": sum(sy.n_sites for sy in systems),
             "e_total_first4": e}
 
 
-def serve_run(n_requests, rate, check_every, dE_tol, budget_gb, grids):
+def serve_run(n_requests, rate, check_every, budget_gb, grids):
     from paper_1507_07666_amd import inputs as I
     from paper_1507_07666_amd import serve
     reqs = I.serving_stream(n_requests, rate=rate, seed=50, grids=grids)
-    cfg = serve.ServeConfig(hbm_budget=int(budget_gb * (1 << 30)), check_every=check_every, dE_tol=dE_tol)
+    cfg = serve.ServeConfig(hbm_budget=int(budget_gb * (1 << 30)), check_every=check_every)
     srv = serve.Server(cfg)
     t0 = time.perf_counter()
     res = srv.run(reqs)
@@ -142,6 +147,26 @@ def serve_run(n_requests, rate, check_every, dE_tol, budget_gb, grids):
     return out
 
 
+def serve_sweep(n_requests, check_every, budget_gb, grids, factors=(0.25, 0.5, 1.0, 2.0)):
+    """Saturation rate first (every request arrives at t = 0: requests/s of the
+    drained queue), then Poisson arrivals of the same seeded stream at the given
+    multiples of it; p50/p99 latency from arrival to the last point's result."""
+    sat = serve_run(n_requests, 1e9, check_every, budget_gb, grids)
+    lam = sat["requests_per_s"]
+    print(f"[serve] saturation {lam:.3f} requests/s, {sat['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    runs = []
+    for f in factors:
+        r = serve_run(n_requests, f * lam, check_every, budget_gb, grids)
+        r["rate_factor"] = f
+        print(f"[serve] rate {f} x saturation: p50 {r['p50_latency_s']:.2f} s, p99 {r['p99_latency_s']:.2f} s, "
+              f"{r['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+        runs.append(r)
+    return {"metric": "serving latency sweep", "saturation_requests_per_s": lam, "saturation": sat,
+            "runs": runs, "data": "synthetic", "dtype": "f32",
+            "config": {"workload": f"serving stream, seed 50, {n_requests} requests (half atoms Z 1..10, half "
+                                   f"8-point scans of CH4/NH3/H2O), grids {list(grids)}, h 0.2"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +175,7 @@ def main():
     ap.add_argument("--workload", default="ne96")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--scheme", default="populations", choices=["populations", "collapsed"])
+    ap.add_argument("--omega", type=float, default=1.0, help="relaxation parameter (populations only)")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -177,15 +203,18 @@ def main():
         print(json.dumps(copy_calibration(args.copy_mib << 20, max(args.steps, 10))), flush=True)
         return
     if args.workload == "h2o_batch":
-        print(json.dumps(h2o_batch_run(args.batch_count, 1e-7, 100, 20000)), flush=True)
+        print(json.dumps(h2o_batch_run(args.batch_count, 100, 20000)), flush=True)
         return
     if args.workload == "serve":
-        print(json.dumps(serve_run(args.requests, args.rate, 100, 1e-7, args.budget_gb, I_SERVE_GRIDS)), flush=True)
+        print(json.dumps(serve_run(args.requests, args.rate, 100, args.budget_gb, I_SERVE_GRIDS)), flush=True)
+        return
+    if args.workload == "serve_sweep":
+        print(json.dumps(serve_sweep(args.requests, 100, args.budget_gb, I_SERVE_GRIDS)), flush=True)
         return
     system = workload(args.workload)
     prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
     scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED
-    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme)
+    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega)
     s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
 
     if args.warmup:
@@ -219,8 +248,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{system.name} atom {system.dims[0]}^3 nodes, h={system.h} bohr, "
                                f"softening {system.softening}, {system.n_orb} orbitals, "
-                               f"{args.precision} {args.scheme}, seed {system.seed}",
+                               f"{args.precision} {args.scheme}, seed {system.seed}"
+                               + (f", omega {args.omega}" if args.omega != 1.0 else ""),
                    "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
+                   "omega": args.omega,
                    "update_variant": variant, "autotune_ms": tune_ms,
                    "parallelism": "single GPU"},
         "e_total": e["e_total"],
@@ -234,6 +265,10 @@ def main():
                            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(tkey) if tkey else None,
                            "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed",
                            "avg_us": avg_s * 1e6, "launches": k1_n, "alg_bytes_per_launch": alg}
+        # the same bytes against what a plain copy kernel reaches on this GPU
+        cp = copy_calibration(678 << 20, 20)
+        out["roofline"]["copy_GBps"] = cp["GBps"]
+        out["roofline"]["frac_of_copy"] = ach / cp["GBps"]
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_steps, threads)

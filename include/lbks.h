@@ -101,7 +101,9 @@ typedef struct lbks_params {
     uint64_t seed;           /* SplitMix64 seed of the initial orbitals */
     double rho_floor;        /* exchange-correlation is zero below this density */
     int32_t scheme;          /* LBKS_SCHEME_* */
-    int32_t reserved[7];     /* must be zero */
+    int32_t stop_checks;     /* stopping rule of lbks_relax: consecutive passing checks needed (0, 1: one) */
+    double deps_tol;         /* > 0: a check also needs |change of sum_j eps_j| < deps_tol */
+    int32_t reserved[4];     /* must be zero */
 } lbks_params;
 
 /* Device binding.  `stream` is a hipStream_t (NULL: the library creates one).
@@ -156,13 +158,16 @@ int lbks_set_nuclei(lbks_ctx *ctx, int32_t n, const double *Z, const double *xyz
 
 /* Run lattice steps (lattice Boltzmann equation per orbital with the
  * orthogonalisation source, then the self-consistent potential).  Steps run
- * in chunks of `check_every`; if dE_tol > 0 the total energy (with the
- * current Hartree potential) is evaluated after each chunk and the call
- * returns LBKS_OK once two consecutive chunk energies differ by less than
- * dE_tol.  The previous chunk energy persists across calls (so splitting a
- * run into calls whose max_steps are multiples of check_every changes
- * nothing) and is forgotten when set_nuclei, set_potential, set_orbitals or
- * lbks_energy change the state.  With dE_tol <= 0 exactly max_steps steps run.  Returns
+ * in chunks of `check_every`; if dE_tol > 0 the energies (with the current
+ * Hartree potential) are evaluated after each chunk.  A check passes when the
+ * total energy changed by less than dE_tol since the previous check and, if
+ * params.deps_tol > 0, the sum of the orbital energies by less than deps_tol
+ * (an eigenvalue-based test in the spirit of the paper's rule on the change of
+ * the eigenvalues); the call returns LBKS_OK after params.stop_checks
+ * consecutive passing checks (at least one).  The previous check and the count
+ * persist across calls (so splitting a run into calls whose max_steps are
+ * multiples of check_every changes nothing) and are forgotten when
+ * set_nuclei, set_potential, set_orbitals or lbks_energy change the state.  With dE_tol <= 0 exactly max_steps steps run.  Returns
  * LBKS_NOT_CONVERGED when max_steps is reached, LBKS_E_NUMERIC if the overlap
  * matrix stops being finite and positive definite, LBKS_E_STATE if no
  * potential was set.  *steps_done (may be NULL) receives the steps run. */
@@ -173,6 +178,20 @@ int lbks_relax(lbks_ctx *ctx, int64_t max_steps, double dE_tol, int32_t check_ev
  * potential for the current density to a relative residual <= 1e-12 (this
  * state change is kept), then evaluates every term of the total energy. */
 int lbks_energy(lbks_ctx *ctx, lbks_energies *out);
+
+/* Forces on the nuclei (host, FP64, F[3 I + c] for nucleus I and axis c, in
+ * hartree per bohr, n_F >= 3 * nuclei) for the current state, as used by
+ * Born-Oppenheimer dynamics (section "Concurrent Dynamics": the ions move on the
+ * surface of the electronic ground state).  Hellmann-Feynman form: with the
+ * density rho of the orthonormalised current orbitals held fixed,
+ *   F_I = Z_I h^3 sum_r rho(r) (r - R_I) / (|r - R_I|^2 + a^2)^(3/2)
+ *         + sum_{J != I} Z_I Z_J (R_I - R_J) / |R_I - R_J|^3,
+ * i.e. minus the gradient of <V_ext|rho> + E_NN.  At a converged state this is
+ * minus the gradient of the total energy up to the lattice's smoothing of the
+ * potential source.  The state is not changed.  LBKS_E_STATE if the potential
+ * came from lbks_set_potential (no nuclei), LBKS_E_INVAL if F is NULL or too
+ * small, LBKS_E_NUMERIC if the overlap or a force is not finite. */
+int lbks_forces(lbks_ctx *ctx, double *F, size_t n_F);
 
 /* Copy the current orthonormal orbitals (host, FP64, [n_orb][z][y][x],
  * n_psi >= n_orb * sites) and optionally the density (host, n_rho >= sites;

@@ -161,6 +161,8 @@ class Params:
     softening: float = 0.05
     rho_floor: float = 1e-14
     occ: Optional[np.ndarray] = None
+    deps_tol: float = 0.0           # stopping rule: > 0 also bounds the change of sum_j eps_j
+    stop_checks: int = 0            # consecutive passing checks needed (0, 1: one)
 
     @property
     def dt(self) -> float:
@@ -204,7 +206,8 @@ class Oracle:
         self.vext = None
         self.e_nn = 0.0
         self.steps = 0
-        self.e_prev = None          # stopping rule: previous chunk energy, kept across relax calls
+        self.e_prev = None          # stopping rule: (energy, sum of eps) of the previous check, kept across relax calls
+        self.passes = 0             # consecutive passing checks
         self.omega_sor = self.L.orc_sor_omega(nx, ny, nz)
 
     # -- inputs
@@ -385,26 +388,35 @@ class Oracle:
         return F
 
     def relax(self, max_steps, dE_tol=0.0, check_every=100, progress=None):
-        """Run steps in chunks of check_every; after each chunk (only if dE_tol > 0)
-        the total energy with the current Hartree potential is compared with the
-        previous chunk's (kept across calls until the state is changed by new
-        nuclei, potential or orbitals, or a Poisson-converged energy evaluation).
-        Returns (0 converged | 1 step limit, steps done).  `progress(steps, energy)`
-        is called after each check."""
+        """Run steps in chunks of check_every.  After each chunk (only if dE_tol > 0)
+        the energies with the current Hartree potential are compared with the
+        previous chunk's: the check passes if the total energy moved by less than
+        dE_tol and, when prm.deps_tol > 0, the sum of the orbital energies by less
+        than deps_tol; the run has converged after prm.stop_checks consecutive
+        passing checks (at least one).  The previous check and the count are kept
+        across calls until the state is changed by new nuclei, potential or
+        orbitals, or a Poisson-converged energy evaluation.  Returns
+        (0 converged | 1 step limit, steps done).  `progress(steps, energy)` is
+        called after each check."""
         done = 0
         check_every = max(1, int(check_every))
+        need = max(1, int(self.prm.stop_checks))
         while done < max_steps:
             n = min(check_every, max_steps - done)
             for _ in range(n):
                 self.step()
             done += n
             if dE_tol > 0:
-                e = self.energies(converge_poisson=False).e_total
+                en = self.energies(converge_poisson=False)
+                e, tr = en.e_total, float(np.sum(en.eps))
                 if progress is not None:
                     progress(done, e)
-                conv = self.e_prev is not None and abs(e - self.e_prev) < dE_tol
-                self.e_prev = e
-                if conv:
+                ok = self.e_prev is not None and abs(e - self.e_prev[0]) < dE_tol
+                if ok and self.prm.deps_tol > 0:
+                    ok = abs(tr - self.e_prev[1]) < self.prm.deps_tol
+                self.passes = self.passes + 1 if ok else 0
+                self.e_prev = (e, tr)
+                if self.passes >= need:
                     return 0, done
         return 1, done
 

@@ -49,8 +49,10 @@ struct lbks_ctx {
     int parity = 0;             // populations live in f0 (0) or f1 (1)
     int64_t steps = 0;
     bool has_potential = false;
-    bool have_prev = false;     // stopping rule: energy of the previous chunk check
+    bool have_prev = false;     // stopping rule: energies of the previous chunk check
     double e_prev = 0.0;
+    double tr_prev = 0.0;       // sum of the orbital energies at that check
+    int passes = 0;             // consecutive passing checks
     double *d_zr = nullptr;     // nuclei table [4 * LBKS_MAX_NUC + 1]
     std::string err;
     // timing of the stream-collide kernel
@@ -137,7 +139,7 @@ void lattice_constants(double D, double *xi, double *chi)
 }
 
 struct Layout {
-    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, g_part, C,
+    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, f_part, g_part, C,
         scal, stage, zr;
     size_t total = 0;
 };
@@ -174,7 +176,9 @@ int validate(const lbks_params *p, std::string &why)
         why = "the collapsed scheme exists only at omega = 1";
         return LBKS_E_INVAL;
     }
-    for (int i = 0; i < 7; ++i)
+    if (p->stop_checks < 0 || p->stop_checks > 1000) { why = "stop_checks must be in [0, 1000]"; return LBKS_E_INVAL; }
+    if (!(p->deps_tol >= 0.0) || !isfinite(p->deps_tol)) { why = "deps_tol must be finite and >= 0"; return LBKS_E_INVAL; }
+    for (int i = 0; i < 4; ++i)
         if (p->reserved[i]) { why = "reserved fields must be zero"; return LBKS_E_INVAL; }
     return 0;
 }
@@ -210,8 +214,9 @@ Layout plan_layout(const lbks_params *p)
     take(L.m_part, (size_t)padded_cols(NMOM) * ntile * 8);
     take(L.e_part, (size_t)padded_cols(2 * no + NEBASE) * ntile * 8);
     take(L.r_part, (size_t)padded_cols(2) * ntile * 8);
+    take(L.f_part, (size_t)padded_cols(3 * NUCG) * ntile * 8);
     {
-        const int widest = std::max(std::max(no * (no + 1) / 2, NMOM), 2 * no + NEBASE);
+        const int widest = std::max(std::max(no * (no + 1) / 2, NMOM), std::max(2 * no + NEBASE, 3 * NUCG));
         take(L.g_part, (size_t)padded_cols(widest) * RG * 8);
     }
     take(L.C, 2 * MAXO * MAXO * 8);
@@ -239,10 +244,33 @@ void dev_free(lbks_ctx *c, void *ptr)
 
 void mark_batch_dirty(lbks_ctx *c);
 
+// The state changed: the stopping rule starts over.
+void reset_rule(lbks_ctx *c)
+{
+    c->have_prev = false;
+    c->passes = 0;
+}
+
+// One check of the stopping rule (see lbks_relax): true once params.stop_checks
+// consecutive checks (at least one) had |dE| < dE_tol and, if deps_tol > 0,
+// |d sum_j eps_j| < deps_tol against the previous check.
+bool rule_check(lbks_ctx *c, double etot, const double *eps, double dE_tol)
+{
+    double tr = 0.0;
+    for (int j = 0; j < c->p.n_orb; ++j) tr += eps[j];
+    const bool pass = c->have_prev && fabs(etot - c->e_prev) < dE_tol &&
+                      (!(c->p.deps_tol > 0.0) || fabs(tr - c->tr_prev) < c->p.deps_tol);
+    c->passes = pass ? c->passes + 1 : 0;
+    c->e_prev = etot;
+    c->tr_prev = tr;
+    c->have_prev = true;
+    return c->passes >= std::max(1, (int)c->p.stop_checks);
+}
+
 int upload_desc(lbks_ctx *c)
 {
     mark_batch_dirty(c);
-    c->have_prev = false;
+    reset_rule(c);
     HIPCHK(c, hipMemcpyAsync(c->d_desc, &c->h, sizeof(InstDesc), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return 0;
@@ -520,11 +548,14 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     h.m_part = (double *)at(L.m_part);
     h.e_part = (double *)at(L.e_part);
     h.r_part = (double *)at(L.r_part);
+    h.f_part = (double *)at(L.f_part);
     h.g_part = (double *)at(L.g_part);
     h.C = (double *)at(L.C);
     h.scal = (double *)at(L.scal);
     h.stage = (double *)at(L.stage);
     c->d_zr = (double *)at(L.zr);
+    h.zr = c->d_zr;
+    h.nnuc = 0;
     c->d_desc = (InstDesc *)at(L.desc);
     Plan &pl = c->plan;
     pl.d_desc = c->d_desc;
@@ -633,6 +664,7 @@ extern "C" int lbks_set_nuclei(lbks_ctx *c, int32_t n, const double *Z, const do
     HIPCHK(c, hipMemcpyAsync(c->d_zr, zr, sizeof(double) * (4 * n + 1), hipMemcpyHostToDevice, c->stream));
     KCHK(c, launch_vext(c->plan, n, c->d_zr, c->stream));
     c->h.e_nn = enn;
+    c->h.nnuc = n;
     int rc = upload_desc(c);
     if (rc) return rc;
     c->has_potential = true;
@@ -644,6 +676,7 @@ extern "C" int lbks_set_potential(lbks_ctx *c, const double *v)
     if (!c || !v) return LBKS_E_INVAL;
     HIPCHK(c, hipMemcpyAsync(c->h.vext, v, sizeof(double) * (size_t)c->h.nsite, hipMemcpyHostToDevice, c->stream));
     c->h.e_nn = 0.0;
+    c->h.nnuc = 0;
     int rc = upload_desc(c);
     if (rc) return rc;
     c->has_potential = true;
@@ -654,7 +687,7 @@ extern "C" int lbks_set_orbitals(lbks_ctx *c, const double *psi)
 {
     if (!c || !psi) return LBKS_E_INVAL;
     const size_t n = (size_t)c->p.n_orb * c->h.nsite;
-    c->have_prev = false;
+    reset_rule(c);
     // new orbitals are a recovery point: after a numeric failure the Hartree
     // potential may hold non-finite values too, so it restarts from zero
     double errf = 0.0;
@@ -699,10 +732,7 @@ extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t
             if ((rc = read_energies(c, &e, &errf))) return rc;
             if (errf != 0.0 || !isfinite(e.e_total))
                 return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
-            const bool conv = c->have_prev && fabs(e.e_total - c->e_prev) < dE_tol;
-            c->e_prev = e.e_total;
-            c->have_prev = true;
-            if (conv) return LBKS_OK;
+            if (rule_check(c, e.e_total, e.eps, dE_tol)) return LBKS_OK;
         }
     }
     double errf = 0.0;
@@ -717,7 +747,7 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
     if (!c || !out) return LBKS_E_INVAL;
     if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     int rc;
-    c->have_prev = false;   // the Hartree relaxation below changes the state
+    reset_rule(c);   // the Hartree relaxation below changes the state
     if ((rc = enqueue_orthonormalise(c))) return rc;
     if (c->p.hartree) {
         if ((rc = enqueue_hartree_boundary(c))) return rc;
@@ -739,6 +769,32 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
     if ((rc = read_energies(c, out, &errf))) return rc;
     if (errf != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
     if (!c->p.hartree) out->poisson_residual = 0.0;
+    return 0;
+}
+
+static_assert(MAXNUC == LBKS_MAX_NUC, "nuclei capacity of the kernels and of the C ABI differ");
+
+extern "C" int lbks_forces(lbks_ctx *c, double *F, size_t n_F)
+{
+    if (!c || !F) return LBKS_E_INVAL;
+    const int nn = c->h.nnuc;
+    if (nn < 1) return fail(c, LBKS_E_STATE, "no nuclei set (forces need lbks_set_nuclei)");
+    if (n_F < (size_t)(3 * nn)) return fail(c, LBKS_E_INVAL, "force buffer too small");
+    int rc;
+    if ((rc = enqueue_orthonormalise(c))) return rc;
+    for (int i0 = 0; i0 < nn; i0 += NUCG) {
+        KCHK(c, launch_force_terms(c->plan, i0, c->stream));
+        KCHK(c, launch_force_finalize(c->plan, i0, c->stream));
+    }
+    double buf[3 * MAXNUC + 1];
+    HIPCHK(c, hipMemcpyAsync(buf, c->h.scal + SC_FORCE, sizeof(double) * 3 * nn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(buf + 3 * nn, c->h.scal + SC_ERR, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (buf[3 * nn] != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+    for (int q = 0; q < 3 * nn; ++q) {
+        if (!isfinite(buf[q])) return fail(c, LBKS_E_NUMERIC, "force not finite");
+        F[q] = buf[q];
+    }
     return 0;
 }
 
@@ -1202,10 +1258,7 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
                     b->dirty = true;
                 } else {
                     lbks_ctx *c = b->members[i];
-                    const bool conv = c->have_prev && fabs(etot - c->e_prev) < dE_tol;
-                    c->e_prev = etot;
-                    c->have_prev = true;
-                    if (conv) {
+                    if (rule_check(c, etot, e + 9, dE_tol)) {
                         st[i] = LBKS_OK;
                         b->running[i] = 0;
                         b->dirty = true;

@@ -19,6 +19,8 @@ constexpr int MAXO = 16;       // orbital capacity of the descriptor
 constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
+constexpr int NUCG = 16;       // nuclei per force-kernel pass
+constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
 
 constexpr int RG = 32;         // first-level workgroups per instance of the finalize kernels
 
@@ -32,7 +34,8 @@ constexpr int SC_ENER = 160;               // lbks_energies prefix: 9 + 16 doubl
 constexpr int SC_RES = 192;                // Poisson relative residual
 constexpr int SC_ERR = 193;                // nonzero: overlap not finite / not SPD
 constexpr int SC_CNT = 194;                // finalize-kernel counter (an unsigned in this slot)
-constexpr int SC_SIZE = 200;
+constexpr int SC_FORCE = 200;              // forces on the nuclei, [MAXNUC][3]
+constexpr int SC_SIZE = 400;
 
 struct InstDesc {
     int nx, ny, nz, n_orb;
@@ -41,7 +44,8 @@ struct InstDesc {
     int ntile_ghost;           // tiles over the six ghost faces
     int ntile_sor;             // tiles over one colour of the SOR sweep
     int ortho, xc, hartree, precision;
-    int scheme, pad0;
+    int scheme;
+    int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
     double h, h3, omega, dt, D, omega_sor, rho_floor, e_nn;
     double occ[MAXO];
     double xi[Q], chi[Q];
@@ -59,7 +63,9 @@ struct InstDesc {
     double *m_part;            // [padded_cols(NMOM)][ntile]
     double *e_part;            // [padded_cols(2*bucket(n_orb) + NEBASE)][ntile]
     double *r_part;            // [padded_cols(2)][ntile]
+    double *f_part;            // [padded_cols(3 NUCG)][ntile]
     double *g_part;            // [padded_cols(widest partial)][RG] first-level column sums
+    const double *zr;          // nuclei: Z, x, y, z per nucleus, then the softening squared
     double *C;                 // [MAXO*MAXO] C, then [MAXO*MAXO] C* (W mode)
     double *scal;              // [SC_SIZE]
     double *stage;             // FP64 staging, (n_orb + 1) * nsite
@@ -116,6 +122,8 @@ int launch_residual(const Plan &pl, hipStream_t st);
 int launch_residual_finalize(const Plan &pl, hipStream_t st);
 int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st);
 int launch_stage_orbitals(const Plan &pl, hipStream_t st);
+int launch_force_terms(const Plan &pl, int i0, hipStream_t st);     // nuclei i0 .. i0 + NUCG - 1
+int launch_force_finalize(const Plan &pl, int i0, hipStream_t st);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
 // dst[i * width + k] = scal_i[SC_ENER + k] (k < 25), dst[i * width + 25] = scal_i[SC_ERR]
 int launch_gather(const double *const *scal, int count, int width, double *dst, hipStream_t st);

@@ -579,6 +579,72 @@ __global__ __launch_bounds__(BS) void k_energy_finalize(const InstDesc *__restri
     E[8] = d.scal[SC_RES];
 }
 
+// ----------------------------------------------------------------- forces
+
+// Per-node Hellmann-Feynman terms of the Born-Oppenheimer forces: for nuclei
+// I = i0 .. i0 + NUCG - 1, rho (r - R_I) / (|r - R_I|^2 + a^2)^(3/2) (three
+// columns per nucleus).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_force_terms(const InstDesc *__restrict__ descs,
+                                                    const int2 *__restrict__ tiles, int i0)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int s = tr.tile * BS + threadIdx.x;
+    const int nn = d.nnuc;
+    const int m = nn - i0 < NUCG ? nn - i0 : NUCG;
+    double v[3 * NUCG];
+#pragma unroll
+    for (int q = 0; q < 3 * NUCG; ++q) v[q] = 0.0;
+    if (s < d.nsite) {
+        const double r = (double)((const T *)d.rho)[s];
+        const int x = s % d.nx, yz = s / d.nx, y = yz % d.ny, z = yz / d.ny;
+        const double rx = node_coord(x, d.nx, d.h), ry = node_coord(y, d.ny, d.h), rz = node_coord(z, d.nz, d.h);
+        const double *zr = d.zr + 4 * i0;
+        const double a2 = d.zr[4 * nn];
+#pragma unroll
+        for (int I = 0; I < NUCG; ++I) {
+            if (I < m) {
+                const double dx = rx - zr[4 * I + 1], dy = ry - zr[4 * I + 2], dz = rz - zr[4 * I + 3];
+                const double d2 = dx * dx + dy * dy + dz * dz + a2;
+                const double w = r / (d2 * sqrt(d2));
+                v[3 * I] = w * dx;
+                v[3 * I + 1] = w * dy;
+                v[3 * I + 2] = w * dz;
+            }
+        }
+    }
+    block_sum_store(v, 3 * m, d.f_part + tr.tile, d.ntile);
+}
+
+// F_I = Z_I h^3 sum_r (the terms above) + sum_{J != I} Z_I Z_J (R_I - R_J) / |R_I - R_J|^3
+// for the same nuclei, into the scalar block.
+__global__ __launch_bounds__(BS) void k_force_finalize(const InstDesc *__restrict__ descs,
+                                                       const int *__restrict__ list, int i0)
+{
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
+    const int nn = d.nnuc;
+    const int m = nn - i0 < NUCG ? nn - i0 : NUCG;
+    __shared__ double tot[3 * NUCG];
+    if (!reduce_columns(d.f_part, d.ntile, 3 * m, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, tot)) return;
+    const int q = threadIdx.x;
+    if (q < 3 * m) {
+        const int I = i0 + q / 3, c = q % 3;
+        const double *zr = d.zr;
+        double f = (zr[4 * I] * d.h3) * tot[q];
+        for (int J = 0; J < nn; ++J) {
+            if (J == I) continue;
+            const double dx = zr[4 * I + 1] - zr[4 * J + 1], dy = zr[4 * I + 2] - zr[4 * J + 2],
+                         dz = zr[4 * I + 3] - zr[4 * J + 3];
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double cc = zr[4 * I] * zr[4 * J] / (r * r * r);
+            f += cc * (c == 0 ? dx : (c == 1 ? dy : dz));
+        }
+        d.scal[SC_FORCE + 3 * i0 + q] = f;
+    }
+}
+
 // Orbitals and density to the FP64 staging buffer.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_stage_orbitals(const InstDesc *__restrict__ descs,
@@ -735,6 +801,21 @@ int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st)
 }
 
 
+
+int launch_force_terms(const Plan &pl, int i0, hipStream_t st)
+{
+    return dispatch_tt(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_force_terms<typename TG::T><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, i0);
+        LAUNCH_CHECK();
+    });
+}
+
+int launch_force_finalize(const Plan &pl, int i0, hipStream_t st)
+{
+    k_force_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst, i0);
+    LAUNCH_CHECK();
+}
 
 int launch_energy_terms(const Plan &pl, hipStream_t st)
 {

@@ -36,7 +36,8 @@ class lbks_params(Structure):
                 ("hartree", c_int32), ("poisson_sweeps", c_int32), ("precision", c_int32),
                 ("softening", c_double), ("init", c_int32), ("init_sigma", c_double),
                 ("init_noise", c_double), ("seed", c_uint64), ("rho_floor", c_double),
-                ("scheme", c_int32), ("reserved", c_int32 * 7)]
+                ("scheme", c_int32), ("stop_checks", c_int32), ("deps_tol", c_double),
+                ("reserved", c_int32 * 4)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -68,6 +69,7 @@ SIGNATURES = {
     "lbks_relax": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int64)]),
     "lbks_energy": (c_int32, [c_void_p, POINTER(lbks_energies)]),
     "lbks_orbitals": (c_int32, [c_void_p, POINTER(c_double), c_size_t, POINTER(c_double), c_size_t]),
+    "lbks_forces": (c_int32, [c_void_p, POINTER(c_double), c_size_t]),
     "lbks_destroy": (None, [c_void_p]),
     "lbks_last_error": (c_char_p, [c_void_p]),
     "lbks_set_potential": (c_int32, [c_void_p, POINTER(c_double)]),
@@ -193,6 +195,14 @@ def lbks_orbitals(ctx, with_rho=True):
     return psi, rho
 
 
+def lbks_forces(ctx, n_nuc):
+    """Forces on the nuclei, [n_nuc][3] hartree/bohr."""
+    F = np.zeros((max(int(n_nuc), 1), 3))
+    rc = load().lbks_forces(ctx, _dptr(F), 3 * int(n_nuc))
+    _check(ctx, rc)
+    return F[:n_nuc]
+
+
 def lbks_destroy(ctx):
     if ctx:
         load().lbks_destroy(ctx)
@@ -267,9 +277,15 @@ class Solver:
 
     def set_nuclei(self, Z, R):
         lbks_set_nuclei(self.ctx, Z, R)
+        self.n_nuc = len(Z)
 
     def set_potential(self, v):
         lbks_set_potential(self.ctx, v)
+        self.n_nuc = 0
+
+    def forces(self):
+        """Hellmann-Feynman forces on the nuclei of the current state, [n][3]."""
+        return lbks_forces(self.ctx, getattr(self, "n_nuc", 0))
 
     def set_orbitals(self, psi):
         lbks_set_orbitals(self.ctx, psi)

@@ -44,18 +44,30 @@ class RequestResult:
         return self.finished - self.arrival
 
 
+# Stopping rule of FP32 solves.  At the fixed point the FP32 total energy moves
+# by up to about 1e-6 Ha from one check to the next, and on the way there it
+# passes a turning point where two checks can agree by chance; the sum of the
+# orbital energies converges linearly in the error of the orbitals and settles
+# to about 3e-7.  A solve stops when the energy moved by less than 2e-6 Ha and
+# the eigenvalue sum by less than 1e-6 Ha on two consecutive checks.
+FP32_RULE = dict(dE_tol=2e-6, deps_tol=1e-6, stop_checks=2)
+
+
 @dataclass
 class ServeConfig:
     hbm_budget: int                 # bytes of device memory the solves may hold
     precision: int = lbks.LBKS_FP32_BULK
     check_every: int = 100
-    dE_tol: float = 1e-7
+    dE_tol: float = FP32_RULE["dE_tol"]
+    deps_tol: float = FP32_RULE["deps_tol"]
+    stop_checks: int = FP32_RULE["stop_checks"]
     chunks_per_call: int = 2        # lattice steps between admissions = chunks_per_call * check_every
     max_steps_per_point: int = 20000
 
 
 def point_params(system, cfg: ServeConfig) -> lbks.lbks_params:
-    return lbks.params_for(system, precision=cfg.precision)
+    return lbks.params_for(system, precision=cfg.precision, deps_tol=cfg.deps_tol,
+                           stop_checks=cfg.stop_checks)
 
 
 def point_bytes(system, cfg: ServeConfig) -> int:

@@ -26,9 +26,11 @@ RUNS = {
     "ch4": (I.ch4, 1e-7, 100, 40000),
     "he32": (I.he_atom, 0.0, 2000, 2000),
 }
+# the H2O references are relaxed well past the FP32 solves' own rule, so that
+# they stand for the fixed point
 for i, s in enumerate(I.h2o_batch(64)):
     if i in (0, 1, 2, 3, 4, 5, 6, 7):
-        RUNS[f"h2o_{i}"] = (lambda s=s: s, 1e-7, 100, 40000)
+        RUNS[f"h2o_{i}"] = (lambda s=s: s, 1e-9, 100, 40000)
 
 N_SAMPLES = 4096
 

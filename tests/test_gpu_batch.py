@@ -71,10 +71,12 @@ def test_batch_equals_alone_fixed_steps(L):
     assert np.isfinite(e0["e_total"])
 
 
-def test_batch_stopping_rule_per_member(L):
-    say("batch convergence")
-    systems = [(I.he_atom().scaled(12, h=0.4), {}), (I.atom(4, 14, h=0.35, seed=9), {}),
-               (I.he_atom().scaled(14, h=0.4), dict(precision=1))]
+@pytest.mark.parametrize("rule", ["energy", "eigenvalue_sum_confirmed"])
+def test_batch_stopping_rule_per_member(L, rule):
+    say("batch convergence", rule)
+    r = {} if rule == "energy" else dict(deps_tol=1e-7, stop_checks=2)
+    systems = [(I.he_atom().scaled(12, h=0.4), dict(r)), (I.atom(4, 14, h=0.35, seed=9), dict(r)),
+               (I.he_atom().scaled(14, h=0.4), dict(precision=1, **r))]
     b = L.Batch()
     members = [b.add_system(sy, **kw) for sy, kw in systems]
     st, steps = b.relax(4000, dE_tol=1e-8, check_every=20)

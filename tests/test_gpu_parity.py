@@ -163,6 +163,28 @@ def test_convergence_control_matches_oracle(L):
     s.close()
 
 
+def test_eigenvalue_sum_rule_with_confirmation_matches_oracle(L):
+    """The stopping rule with deps_tol and stop_checks: same (status, steps) as the
+    oracle, also when the run is split into calls of whole chunks."""
+    system = I.ne_atom().scaled(14, h=0.4)
+    say("relax rule with eigenvalue sum and confirmation")
+    s, o = make_pair(L, system, deps_tol=1e-6, stop_checks=2)
+    o.prm.deps_tol, o.prm.stop_checks = 1e-6, 2
+    got = s.relax(5000, dE_tol=1e-6, check_every=20)
+    ref = o.relax(5000, dE_tol=1e-6, check_every=20)
+    assert got == ref and got[0] == 0, (got, ref)
+    s.close()
+    s, _ = make_pair(L, system, deps_tol=1e-6, stop_checks=2)
+    tot = 0
+    while True:
+        rc, n = s.relax(40, dE_tol=1e-6, check_every=20)
+        tot += n
+        if rc == 0:
+            break
+    assert tot == ref[1]
+    s.close()
+
+
 def test_error_paths(L):
     system = I.he_atom().scaled(12)
     say("error paths")

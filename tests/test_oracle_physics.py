@@ -193,6 +193,36 @@ def test_relax_stopping_rule(oracle_mod):
     assert ra == (0, tot) and a.energies(False).e_total == b.energies(False).e_total
 
 
+def test_relax_rule_with_eigenvalue_sum_and_confirmation(oracle_mod):
+    """The stopping rule with deps_tol and stop_checks stops where the recorded
+    sequence of check energies says it should: the first check after which
+    stop_checks consecutive checks had |dE| < dE_tol and |d sum eps| < deps_tol."""
+    O = oracle_mod
+    from paper_1507_07666_amd import inputs as I
+    s = I.ne_atom().scaled(14, h=0.4)
+    every, dE_tol, deps_tol, need = 20, 1e-6, 1e-5, 2
+    rec = O.oracle_for(s)
+    seq = []
+    for _ in range(60):
+        rec.relax(every)
+        en = rec.energies(converge_poisson=False)       # reads only
+        seq.append((en.e_total, float(np.sum(en.eps))))
+    expect, run = None, 0
+    for k in range(1, len(seq)):
+        ok = abs(seq[k][0] - seq[k - 1][0]) < dE_tol and abs(seq[k][1] - seq[k - 1][1]) < deps_tol
+        run = run + 1 if ok else 0
+        if run >= need:
+            expect = (k + 1) * every
+            break
+    assert expect is not None
+    o = O.oracle_for(s, deps_tol=deps_tol, stop_checks=need)
+    assert o.relax(60 * every, dE_tol, every) == (0, expect)
+    # energy alone, one check: never later than the confirmed rule
+    o1 = O.oracle_for(s)
+    rc1, n1 = o1.relax(60 * every, dE_tol, every)
+    assert rc1 == 0 and n1 <= expect
+
+
 def test_nuclear_repulsion_closed_form(oracle_mod):
     O = oracle_mod
     prm = O.Params((4, 4, 4), 0.5, 1, 2)
