@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default update-kernel variant")
+    ap.add_argument("--variant", type=int, default=None, help="fix the update-kernel variant (no autotuning)")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--rate", type=float, default=2.0, help="serving arrivals per second")
@@ -217,9 +218,14 @@ def main():
     solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega)
     s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
 
+    if args.variant is not None:
+        solver.set_variant(args.variant)
     if args.warmup:
         solver.relax(args.warmup)
-    variant, tune_ms = (solver.variant(), None) if args.no_autotune else solver.autotune(reps=5, force=True)
+    if args.no_autotune or args.variant is not None:
+        variant, tune_ms = solver.variant(), None
+    else:
+        variant, tune_ms = solver.autotune(reps=5, force=True)
     torch.cuda.synchronize()
     if not args.no_timing:
         solver.set_timing(True)

@@ -253,9 +253,11 @@ int lbks_get_variant(const lbks_ctx *ctx);
  * (-1 when the cache answered).  LBKS_E_STATE if no potential is set. */
 int lbks_autotune(lbks_ctx *ctx, int32_t reps, int32_t force, int32_t *chosen, double *avg_ms);
 
-/* Plain device-to-device copy of `bytes` on `stream` with the library's own
- * copy kernel (device pointers, 16-byte aligned); used to calibrate memory
- * counters against a kernel of known traffic. */
+/* Plain device-to-device copy of `bytes` (a multiple of 16) on `stream` with
+ * the library's own copy kernel (device pointers, 16-byte aligned; one 16-byte
+ * element per lane, non-temporal loads and stores): the bandwidth reference and
+ * the calibration of memory counters against a kernel of known traffic.
+ * LBKS_E_INVAL on a bad size or alignment. */
 int lbks_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
 
 /* ---- batches: many solves advanced together, one launch per kernel ---- */

@@ -659,10 +659,15 @@ __global__ __launch_bounds__(BS) void k_stage_orbitals(const InstDesc *__restric
     d.stage[(size_t)d.n_orb * N + s] = (double)((const T *)d.rho)[s];
 }
 
-__global__ void k_copy16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n16)
+// Plain copy, 16 bytes per lane, one element per lane over an exact grid, with
+// non-temporal loads and stores like the populations of the update kernel: the
+// bandwidth reference and the HBM-counter calibration.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void k_copy16(u32x4 *__restrict__ dst, const u32x4 *__restrict__ src, size_t n16)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // Energies and error flags of many instances into one buffer (one read-back).
@@ -851,10 +856,10 @@ int launch_gather(const double *const *scal, int count, int width, double *dst, 
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st)
 {
     const size_t n16 = bytes / 16;
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 256 * 64) blocks = 256 * 64;
+    const size_t blocks = (n16 + 255) / 256;
     if (blocks == 0) return 0;
-    k_copy16<<<(unsigned)blocks, 256, 0, st>>>((uint4 *)dst, (const uint4 *)src, n16);
+    if (blocks > 0x7fffffff) return (int)hipErrorInvalidValue;
+    k_copy16<<<(unsigned)blocks, 256, 0, st>>>((u32x4 *)dst, (const u32x4 *)src, n16);
     LAUNCH_CHECK();
 }
 
