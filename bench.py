@@ -131,6 +131,39 @@ def h2o_batch_run(count, check_every, max_steps):
             "e_total_first4": e}
 
 
+def bo_md_run(n_steps, n=80):
+    """Born-Oppenheimer dynamics of one H2O (80^3 at 0.2 bohr, FP32 bulk): velocity
+    Verlet with dt = 0.09 fs, the electrons relaxed by the FP32 rule at every nuclear
+    step from the previous step's orbitals.  Returns time per nuclear step, lattice
+    steps per nuclear step and the total-energy excursion."""
+    import numpy as np
+    import torch
+    from paper_1507_07666_amd import dynamics as Dy
+    from paper_1507_07666_amd import inputs as I
+    from paper_1507_07666_amd import lbks
+    from paper_1507_07666_amd.serve import FP32_RULE
+    sy = I.h2o_from_geometry(1.85, 1.75, 108.0, n, seed=11)
+    s = lbks.Solver(lbks.params_for(sy, precision=lbks.LBKS_FP32_BULK, deps_tol=FP32_RULE["deps_tol"],
+                                    stop_checks=FP32_RULE["stop_checks"]))
+    s.set_nuclei(sy.Z, sy.R)
+    rule = Dy.ElectronRule(dE_tol=FP32_RULE["dE_tol"], check_every=50)
+    s.relax(20000, rule.dE_tol, rule.check_every)            # ground state at the start
+    masses = [16.0 * Dy.AMU, Dy.PROTON_MASS, Dy.PROTON_MASS]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = Dy.bo_md(s, sy.Z, np.array(sy.R), np.zeros((3, 3)), masses, 0.09 * Dy.FS, n_steps, rule=rule)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s.close()
+    return {"metric": "Born-Oppenheimer nuclear steps/s", "value": n_steps / wall, "unit": "nuclear steps/s",
+            "ms_per_nuclear_step": 1e3 * wall / n_steps,
+            "lattice_steps_per_nuclear_step": float(np.mean(tr.lattice_steps[1:])),
+            "e_total_excursion_Ha": float(np.max(np.abs(tr.e_total - tr.e_total[0]))),
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"H2O {n}^3 at 0.2 bohr, softening 0.05, FP32 bulk, velocity Verlet dt 0.09 fs, "
+                                   f"{n_steps} steps from rest at O-H 1.85/1.75 bohr, 108 deg"}}
+
+
 def serve_run(n_requests, rate, check_every, budget_gb, grids):
     from paper_1507_07666_amd import inputs as I
     from paper_1507_07666_amd import serve
@@ -208,6 +241,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(serve_run(args.requests, args.rate, 100, args.budget_gb, I_SERVE_GRIDS)), flush=True)
+        return
+    if args.workload == "bo_md":
+        print(json.dumps(bo_md_run(max(2, args.steps // 15))), flush=True)
         return
     if args.workload == "serve_sweep":
         print(json.dumps(serve_sweep(args.requests, 100, args.budget_gb, I_SERVE_GRIDS)), flush=True)
