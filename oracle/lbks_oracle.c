@@ -402,7 +402,7 @@ void orc_forces(int nx, int ny, int nz, double h, int nnuc, const double *Z, con
     }
 }
 
-enum { ORC_XC_NONE = 0, ORC_XC_X = 1, ORC_XC_X_LYPLOCAL = 2, ORC_XC_X_PZ81 = 3 };
+enum { ORC_XC_NONE = 0, ORC_XC_X = 1, ORC_XC_X_LYPLOCAL = 2, ORC_XC_X_PZ81 = 3, ORC_XC_B88_LYP = 4 };
 
 /*
  * Local exchange-correlation per unit charge (eps) and potential (v = d(rho eps)/drho)
@@ -456,6 +456,129 @@ void orc_xc(int kind, i64 nsite, const double *rho, double floor, double *ex, do
 {
 #pragma omp parallel for schedule(static)
     for (i64 s = 0; s < nsite; ++s) orc_xc_point(kind, rho[s], floor, ex + s, ec + s, vx + s, vc + s);
+}
+
+/*
+ * Gradient-corrected exchange-correlation (the functionals the paper's Table 1
+ * compares with: Becke 1988 exchange and Lee-Yang-Parr 1988 correlation),
+ * spin-unpolarised, as energy densities per volume f(rho, sigma), sigma = |grad rho|^2.
+ *
+ * Becke 1988, per spin density n = rho/2 with gradient g = |grad rho|/2:
+ *   e_s = -C n^(4/3) - beta n^(4/3) H(x),  x = g / n^(4/3),
+ *   H(x) = x^2 / (1 + 6 beta x asinh x),  C = (3/4)(6/pi)^(1/3),  beta = 0.0042;
+ * the total is 2 e_s, which at sigma = 0 is Slater exchange.
+ *
+ * Lee-Yang-Parr 1988, closed shell, u = rho^(-1/3):
+ *   E_c = -a int [rho + b rho^(-2/3) (C_F rho^(5/3) - 2 t_W + (t_W + lap rho / 2) / 9)
+ *                 e^(-c u)] / (1 + d u),   t_W = sigma / (8 rho) - lap rho / 8.
+ * Reading: the Laplacian terms are integrated by parts (the density vanishes at
+ * the box walls), which leaves f_c = f0(rho) + f1(rho) sigma with
+ *   f0 = -a rho (1 + b C_F e^(-c u)) / (1 + d u)            (the local form above),
+ *   f1 = a b rho^(-5/3) e^(-c u) / (1 + d u) (3 + 7 delta) / 72,
+ *   delta = c u + d u / (1 + d u).
+ * Below `floor` everything is zero.  Outputs: energy densities and their partial
+ * derivatives with respect to rho and sigma, exchange and correlation apart.
+ */
+void orc_gga_point(double rho, double sigma, double floor, double *fx, double *fc, double *fx_r, double *fc_r,
+                   double *fx_s, double *fc_s)
+{
+    const double pi = 3.14159265358979323846;
+    *fx = *fc = *fx_r = *fc_r = *fx_s = *fc_s = 0.0;
+    if (!(rho >= floor) || rho <= 0.0) return;
+    /* Becke 1988 */
+    {
+        const double beta = 0.0042, C = 0.75 * cbrt(6.0 / pi);
+        double n = 0.5 * rho, n13 = cbrt(n), n43 = n * n13;
+        double x = 0.5 * sqrt(sigma) / n43;
+        double as = asinh(x);
+        double q = 1.0 + 6.0 * beta * x * as;
+        double H = x * x / q;
+        /* H'(x) / x, finite at x = 0 */
+        double Hpx = (2.0 * q - 6.0 * beta * x * (as + x / sqrt(1.0 + x * x))) / (q * q);
+        double es = -C * n43 - beta * n43 * H;
+        *fx = 2.0 * es;
+        /* d(2 e_s)/d rho = d e_s/dn at fixed g; d/dn = -(4/3) C n^(1/3) - (4/3) beta n^(1/3) (H - x H') */
+        *fx_r = -(4.0 / 3.0) * C * n13 - (4.0 / 3.0) * beta * n13 * (H - x * x * Hpx);
+        /* d(2 e_s)/d sigma = -beta H'(x) / (2 sqrt(sigma)) = -beta (H'/x) / (4 n^(4/3)) */
+        *fx_s = -beta * Hpx / (4.0 * n43);
+    }
+    /* Lee-Yang-Parr 1988 */
+    {
+        const double a = 0.04918, b = 0.132, c = 0.2533, d = 0.349;
+        const double CF = 0.3 * pow(3.0 * pi * pi, 2.0 / 3.0);
+        double u = 1.0 / cbrt(rho);
+        double e = exp(-c * u);
+        double den = 1.0 + d * u;
+        /* f0 and its derivative: the local form, f0 = rho eps_c, f0' = v_c */
+        double num = 1.0 + b * CF * e;
+        double g = num / den;
+        double gp = (-b * CF * c * e * den - d * num) / (den * den);
+        double f0 = -a * rho * g;
+        double f0p = -a * (g - (u / 3.0) * gp);
+        double delta = c * u + d * u / den;
+        double A = pow(rho, -5.0 / 3.0) * e / den;   /* rho^(-5/3) e^(-cu) / (1 + du) */
+        double f1 = a * b * A * (3.0 + 7.0 * delta) / 72.0;
+        /* f1' = a b A / (216 rho) [(delta - 5)(3 + 7 delta) - 7 u (c + d / (1 + du)^2)] */
+        double f1p = a * b * A / (216.0 * rho) * ((delta - 5.0) * (3.0 + 7.0 * delta) - 7.0 * u * (c + d / (den * den)));
+        *fc = f0 + f1 * sigma;
+        *fc_r = f0p + f1p * sigma;
+        *fc_s = f1;
+    }
+}
+
+/*
+ * Gradient-corrected exchange-correlation on the grid.  sigma = |D rho|^2 with
+ * central differences D_a rho = (rho(r + e_a) - rho(r - e_a)) / 2h and rho = 0
+ * outside the box; the potential is the exact derivative of the discrete energy
+ * h^3 sum_r f(rho_r, sigma_r) with respect to rho_s, divided by h^3:
+ *   v = df/drho - sum_a D_a [2 (df/dsigma) D_a rho]   (same central differences).
+ * ex, ec: energy per particle (f / rho, zero where rho = 0) so that E = h^3 <rho|e>;
+ * vx, vc: the exchange and correlation parts of v.
+ */
+void orc_gga(int nx, int ny, int nz, double h, const double *rho, double floor, double *ex, double *ec,
+             double *vx, double *vc)
+{
+    const i64 N = (i64)nx * ny * nz;
+    double *gx = (double *)calloc((size_t)N * 6, sizeof(double));   /* 2 f_s D_a rho, exchange then correlation */
+    const i64 sx = 1, sy = nx, sz = (i64)nx * ny;
+    const double ih2 = 1.0 / (2.0 * h);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                i64 s = ((i64)k * ny + j) * nx + i;
+                double xp = i + 1 < nx ? rho[s + sx] : 0.0, xm = i > 0 ? rho[s - sx] : 0.0;
+                double yp = j + 1 < ny ? rho[s + sy] : 0.0, ym = j > 0 ? rho[s - sy] : 0.0;
+                double zp = k + 1 < nz ? rho[s + sz] : 0.0, zm = k > 0 ? rho[s - sz] : 0.0;
+                double D[3] = {(xp - xm) * ih2, (yp - ym) * ih2, (zp - zm) * ih2};
+                double sigma = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+                double fx, fc, fxr, fcr, fxs, fcs;
+                orc_gga_point(rho[s], sigma, floor, &fx, &fc, &fxr, &fcr, &fxs, &fcs);
+                ex[s] = rho[s] > 0.0 ? fx / rho[s] : 0.0;
+                ec[s] = rho[s] > 0.0 ? fc / rho[s] : 0.0;
+                vx[s] = fxr;
+                vc[s] = fcr;
+                for (int a = 0; a < 3; ++a) {
+                    gx[(i64)a * N + s] = 2.0 * fxs * D[a];
+                    gx[(i64)(3 + a) * N + s] = 2.0 * fcs * D[a];
+                }
+            }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                i64 s = ((i64)k * ny + j) * nx + i;
+                for (int part = 0; part < 2; ++part) {
+                    const double *G = gx + (i64)3 * part * N;
+                    double div = 0.0;
+                    div += ((i + 1 < nx ? G[s + sx] : 0.0) - (i > 0 ? G[s - sx] : 0.0)) * ih2;
+                    div += ((j + 1 < ny ? G[N + s + sy] : 0.0) - (j > 0 ? G[N + s - sy] : 0.0)) * ih2;
+                    div += ((k + 1 < nz ? G[2 * N + s + sz] : 0.0) - (k > 0 ? G[2 * N + s - sz] : 0.0)) * ih2;
+                    if (part == 0) vx[s] -= div;
+                    else vc[s] -= div;
+                }
+            }
+    free(gx);
 }
 
 /* ---------------------------------------------------- collide and stream */

@@ -31,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbks_oracle.so")
 SRC_PATH = os.path.join(_HERE, "lbks_oracle.c")
 
-XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81 = 0, 1, 2, 3
+XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81, XC_B88_LYP = 0, 1, 2, 3, 4
 Q = 19
 
 _lib = None
@@ -79,6 +79,8 @@ def lib():
             "orc_enn": (D, [I, P, P]),
             "orc_forces": (None, [I, I, I, D, I, P, P, D, P, P]),
             "orc_xc": (None, [I, i64, P, D, P, P, P, P]),
+            "orc_gga_point": (None, [D, D, D, P, P, P, P, P, P]),
+            "orc_gga": (None, [I, I, I, D, P, D, P, P, P, P]),
             "orc_collide": (None, [I, i64, D, D, P, P, P, P, P, P, P]),
             "orc_stream": (None, [I, I, I, I, P, P, P]),
             "orc_equilibrium": (None, [I, i64, P, P, P]),
@@ -126,12 +128,25 @@ def time_step(omega: float, D: float, h: float) -> float:
     return 2.0 * (1.0 / omega - 0.5) * D * h * h
 
 
-def xc_fields(kind: int, rho: np.ndarray, floor: float = 1e-14):
+def xc_fields(kind: int, rho: np.ndarray, floor: float = 1e-14, dims=None, h=None):
+    """Per-node exchange and correlation energies per particle and potentials.
+    The gradient-corrected kind (XC_B88_LYP) needs the grid (dims, h)."""
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     n = rho.size
     ex, ec, vx, vc = (np.zeros_like(rho) for _ in range(4))
-    lib().orc_xc(kind, n, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
+    if kind == XC_B88_LYP:
+        nx, ny, nz = dims
+        lib().orc_gga(nx, ny, nz, h, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
+    else:
+        lib().orc_xc(kind, n, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
     return ex, ec, vx, vc
+
+
+def gga_point(rho: float, sigma: float, floor: float = 1e-14):
+    """(f_x, f_c, df_x/drho, df_c/drho, df_x/dsigma, df_c/dsigma) of B88 + LYP."""
+    out = [ctypes.c_double() for _ in range(6)]
+    lib().orc_gga_point(rho, sigma, floor, *[ctypes.byref(o) for o in out])
+    return tuple(o.value for o in out)
 
 
 def apply_sw(dims, v, wts, u):
@@ -298,7 +313,7 @@ class Oracle:
         V = self.vext.copy()
         if self.prm.hartree:
             V += self.vh_interior()
-        ex, ec, vx, vc = xc_fields(self.prm.xc, rho, self.prm.rho_floor)
+        ex, ec, vx, vc = xc_fields(self.prm.xc, rho, self.prm.rho_floor, self.prm.dims, self.prm.h)
         if self.prm.xc != XC_NONE:
             V += vx
             V += vc

@@ -1,0 +1,140 @@
+"""Pins of the oracle's gradient-corrected exchange-correlation (Becke 1988
+exchange + Lee-Yang-Parr 1988 correlation, the functionals of the paper's
+Table 1), spin-unpolarised.
+
+  * sigma = 0: the energy densities and potentials are the (separately pinned)
+    Slater exchange and local LYP correlation;
+  * Becke's gradient coefficient: f_x(rho, sigma) - f_x(rho, 0) -> -beta
+    sum_spins |grad rho_s|^2 / rho_s^(4/3) = -beta 2^(1/3) sigma / rho^(4/3) for
+    small sigma, beta = 0.0042;
+  * Becke's asymptote: for an exponential spin density the exchange energy per
+    particle follows the leading-order closed form (a r / 3) / ln(2x) * (-1/2r),
+    which does not involve beta;
+  * LYP's gradient terms: the integrated-by-parts form f0 + f1 sigma integrates,
+    for smooth radial densities, to the same energy as LYP's original form with
+    t_W and the Laplacian, written out independently here;
+  * the partial derivatives match finite differences of the energy densities;
+  * on the grid, the potential is the exact derivative of the discrete energy
+    h^3 sum f(rho, |D rho|^2) (central differences D), by finite differences.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import simpson
+
+LYP = dict(a=0.04918, b=0.132, c=0.2533, d=0.349)
+CF = 0.3 * (3.0 * math.pi ** 2) ** (2.0 / 3.0)
+
+
+def test_zero_gradient_reduces_to_local_functionals(oracle_mod):
+    O = oracle_mod
+    for rho in (1e-8, 1e-4, 0.03, 0.7, 5.0, 120.0):
+        fx, fc, fxr, fcr, fxs, fcs = O.gga_point(rho, 0.0)
+        ex, ec, vx, vc = O.xc_fields(O.XC_X_LYPLOCAL, np.array([rho]))
+        assert fx == pytest.approx(rho * ex[0], rel=1e-13)
+        assert fc == pytest.approx(rho * ec[0], rel=1e-13)
+        assert fxr == pytest.approx(vx[0], rel=1e-12)
+        assert fcr == pytest.approx(vc[0], rel=1e-12)
+    assert O.gga_point(1e-15, 1.0) == (0.0,) * 6          # below the floor
+
+
+def test_becke_gradient_coefficient(oracle_mod):
+    O = oracle_mod
+    beta = 0.0042
+    for rho in (0.01, 0.3, 4.0):
+        sigma = 1e-8 * rho ** (8.0 / 3.0)
+        d = O.gga_point(rho, sigma)[0] - O.gga_point(rho, 0.0)[0]
+        ref = -beta * 2.0 * (sigma / 4.0) / (rho / 2.0) ** (4.0 / 3.0)      # two spins, rho_s = rho / 2
+        assert d == pytest.approx(ref, rel=1e-6)
+
+
+@pytest.mark.parametrize("r", [60.0, 120.0])
+def test_becke_asymptote(oracle_mod, r):
+    """Spin density n = e^(-a r) / pi (rho = 2n): x = |grad n| / n^(4/3) grows
+    without bound and e_s / n -> -(a/6) / ln(2x) = -1/(2r) (ar/3) / ln(2x)."""
+    O = oracle_mod
+    a = 2.0
+    n = math.exp(-a * r) / math.pi
+    g = a * n
+    rho, sigma = 2.0 * n, (2.0 * g) ** 2
+    fx = O.gga_point(rho, sigma, 0.0)[0]
+    e_per_spin_particle = fx / rho
+    x = g / n ** (4.0 / 3.0)
+    lead = -(a / 6.0) / math.log(2.0 * x)
+    assert e_per_spin_particle == pytest.approx(lead, rel=2e-3)
+    assert e_per_spin_particle * (-2.0 * r) == pytest.approx((a * r / 3.0) / math.log(2.0 * x), rel=2e-3)
+
+
+def lyp_original_density(rho, grad2, lap):
+    """Integrand of LYP 1988 (closed shell) with t_W and the Laplacian."""
+    a, b, c, d = LYP["a"], LYP["b"], LYP["c"], LYP["d"]
+    u = rho ** (-1.0 / 3.0)
+    tw = grad2 / (8.0 * rho) - lap / 8.0
+    br = CF * rho ** (5.0 / 3.0) - 2.0 * tw + (tw + 0.5 * lap) / 9.0
+    return -a * (rho + b * rho ** (-2.0 / 3.0) * br * np.exp(-c * u)) / (1.0 + d * u)
+
+
+@pytest.mark.parametrize("shape", ["gauss2", "slater_like"])
+def test_lyp_integration_by_parts(oracle_mod, shape):
+    O = oracle_mod
+    r = np.linspace(1e-5, 14.0, 400001)
+    if shape == "gauss2":
+        # rho = A e^(-al r^2) + B e^(-be r^2)
+        A, al, B, be = 3.0, 1.7, 0.4, 0.35
+        e1, e2 = A * np.exp(-al * r * r), B * np.exp(-be * r * r)
+        rho = e1 + e2
+        d1 = -2 * al * r * e1 - 2 * be * r * e2
+        d2 = (4 * al * al * r * r - 2 * al) * e1 + (4 * be * be * r * r - 2 * be) * e2
+    else:
+        # rho = A e^(-k sqrt(r^2 + s^2)): exponential tail, smooth at the origin
+        A, k, s0 = 2.5, 2.2, 0.3
+        q = np.sqrt(r * r + s0 * s0)
+        rho = A * np.exp(-k * q)
+        d1 = -k * r / q * rho
+        d2 = (k * k * r * r / (q * q) - k * s0 * s0 / q ** 3) * rho
+    lap = d2 + 2.0 * d1 / r
+    orig = lyp_original_density(rho, d1 * d1, lap)
+    mine = np.array([O.gga_point(x, y, 0.0)[1] for x, y in zip(rho[::20], (d1 * d1)[::20])])
+    w = 4.0 * math.pi * r * r
+    E_orig = simpson(w * orig, x=r)
+    E_mine = simpson((w * 1.0)[::20] * mine, x=r[::20])
+    assert E_mine == pytest.approx(E_orig, rel=1e-7), (E_mine, E_orig)
+
+
+def test_partial_derivatives(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        rho = 10 ** rng.uniform(-4, 1.5)
+        sigma = rho ** (8.0 / 3.0) * 10 ** rng.uniform(-3, 2)
+        f = O.gga_point(rho, sigma)
+        for which, (vr, vs) in ((0, (2, 4)), (1, (3, 5))):
+            hr, hs = 1e-4 * rho, 1e-4 * sigma
+            dr = (O.gga_point(rho + hr, sigma)[which] - O.gga_point(rho - hr, sigma)[which]) / (2 * hr)
+            ds = (O.gga_point(rho, sigma + hs)[which] - O.gga_point(rho, sigma - hs)[which]) / (2 * hs)
+            assert f[vr] == pytest.approx(dr, rel=1e-6, abs=1e-12), (which, rho, sigma)
+            assert f[vs] == pytest.approx(ds, rel=1e-6, abs=1e-12), (which, rho, sigma)
+
+
+def test_grid_potential_is_the_derivative_of_the_discrete_energy(oracle_mod):
+    O = oracle_mod
+    from paper_1507_07666_amd.inputs import radius2
+    dims, h = (14, 12, 10), 0.3
+    r2 = radius2(dims, h).ravel()
+    rng = np.random.default_rng(9)
+    rho = 2.0 * np.exp(-1.3 * np.sqrt(r2 + 0.04)) * (1.0 + 0.2 * rng.random(r2.size))
+
+    def energy(rr):
+        ex, ec, _, _ = O.xc_fields(O.XC_B88_LYP, rr, 1e-14, dims, h)
+        return h ** 3 * float(np.sum(rr * (ex + ec)))
+
+    _, _, vx, vc = O.xc_fields(O.XC_B88_LYP, rho, 1e-14, dims, h)
+    for trial in range(4):
+        delta = np.zeros_like(rho)
+        idx = rng.choice(rho.size, 25, replace=False)
+        delta[idx] = rng.standard_normal(25) * rho[idx]
+        eps = 1e-5
+        fd = (energy(rho + eps * delta) - energy(rho - eps * delta)) / (2 * eps)
+        an = h ** 3 * float(np.dot(vx + vc, delta))
+        assert an == pytest.approx(fd, rel=1e-7, abs=1e-13), (trial, an, fd)
