@@ -53,13 +53,18 @@ extern "C" {
 #define LBKS_ORTHO_GS 0
 #define LBKS_ORTHO_W 1
 
-/* local exchange-correlation (the paper leaves V_xc open): none, Slater
- * exchange, Slater + Lee-Yang-Parr correlation at zero density gradient,
- * Slater + Perdew-Zunger 1981. */
+/* exchange-correlation (the paper leaves V_xc open): none, Slater exchange,
+ * Slater + Lee-Yang-Parr correlation at zero density gradient, Slater +
+ * Perdew-Zunger 1981, or the gradient-corrected functionals the paper's Table 1
+ * compares with: Becke 1988 exchange + Lee-Yang-Parr 1988 correlation
+ * (spin-unpolarised; the gradient is taken by central differences and the
+ * potential is the exact derivative of the discrete energy; 32 more bytes of
+ * device memory per node). */
 #define LBKS_XC_NONE 0
 #define LBKS_XC_X 1
 #define LBKS_XC_X_LYPLOCAL 2
 #define LBKS_XC_X_PZ81 3
+#define LBKS_XC_B88_LYP 4
 
 /* precision: everything in FP64, or populations, orbitals, density and
  * potential stored and streamed in FP32 while the overlap, Cholesky factor,
@@ -175,8 +180,10 @@ int lbks_relax(lbks_ctx *ctx, int64_t max_steps, double dE_tol, int32_t check_ev
                int64_t *steps_done);
 
 /* Energies of the current state (host struct).  First relaxes the Hartree
- * potential for the current density to a relative residual <= 1e-12 (this
- * state change is kept), then evaluates every term of the total energy. */
+ * potential for the current density to a relative residual <= 1e-12, or to
+ * the roundoff floor of a fine grid (the residual <= 1e-9 and no more than 10 %
+ * below its value 50 sweeps earlier); this state change is kept.  Then
+ * evaluates every term of the total energy. */
 int lbks_energy(lbks_ctx *ctx, lbks_energies *out);
 
 /* Forces on the nuclei (host, FP64, F[3 I + c] for nucleus I and axis c, in

@@ -343,13 +343,21 @@ class Oracle:
         return psihat, self.density(psihat)
 
     def converge_poisson(self, rho, tol=1e-12, block=10, max_sweeps=200000):
+        """Blocks of `block` SOR sweeps until the relative residual is <= tol, or until
+        it has reached the roundoff floor: <= 1e-9 and no more than 10 % below its
+        value five blocks earlier."""
         self.hartree_boundary(rho)
         sweeps = 0
         res = self.poisson_residual(rho)
+        hist = [res]
         while res > tol and sweeps < max_sweeps:
+            k = len(hist) - 1
+            if k >= 5 and res <= 1e-9 and res >= 0.9 * hist[k - 5]:
+                break
             self.sor(rho, block)
             sweeps += block
             res = self.poisson_residual(rho)
+            hist.append(res)
         return res, sweeps
 
     def energies(self, converge_poisson=True, tol=1e-12) -> Energies:

@@ -67,7 +67,7 @@ struct lbks_ctx {
 // One launch group of a batch: members sharing every template and sequence choice.
 struct BatchGroup {
     int precision = 0, no = 1, scheme = 0, hartree = 1, sweeps = 2, variant = 0;
-    bool wmode = false;
+    bool wmode = false, gga = false;
     std::vector<int> members;   // indices into lbks_batch::members
     Plan plan{};
 };
@@ -139,7 +139,7 @@ void lattice_constants(double D, double *xi, double *chi)
 }
 
 struct Layout {
-    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, f_part, g_part, C,
+    Buf desc, f0, f1, psi, psihat, psistar, rho, V, Vd, vext, vh, s_part, m_part, e_part, r_part, f_part, gga, g_part, C,
         scal, stage, zr;
     size_t total = 0;
 };
@@ -165,7 +165,7 @@ int validate(const lbks_params *p, std::string &why)
         return LBKS_E_INVAL;
     }
     if (p->ortho != LBKS_ORTHO_GS && p->ortho != LBKS_ORTHO_W) { why = "bad ortho"; return LBKS_E_INVAL; }
-    if (p->xc < LBKS_XC_NONE || p->xc > LBKS_XC_X_PZ81) { why = "bad xc"; return LBKS_E_INVAL; }
+    if (p->xc < LBKS_XC_NONE || p->xc > LBKS_XC_B88_LYP) { why = "bad xc"; return LBKS_E_INVAL; }
     if (p->poisson_sweeps < 0 || p->poisson_sweeps > 64) { why = "poisson_sweeps out of [0, 64]"; return LBKS_E_INVAL; }
     if (p->precision != LBKS_FP64 && p->precision != LBKS_FP32_BULK) { why = "bad precision"; return LBKS_E_INVAL; }
     if (!(p->softening >= 0.0)) { why = "softening must be >= 0"; return LBKS_E_INVAL; }
@@ -215,6 +215,7 @@ Layout plan_layout(const lbks_params *p)
     take(L.e_part, (size_t)padded_cols(2 * no + NEBASE) * ntile * 8);
     take(L.r_part, (size_t)padded_cols(2) * ntile * 8);
     take(L.f_part, (size_t)padded_cols(3 * NUCG) * ntile * 8);
+    take(L.gga, p->xc == LBKS_XC_B88_LYP ? 4 * N * 8 : 0);
     {
         const int widest = std::max(std::max(no * (no + 1) / 2, NMOM), std::max(2 * no + NEBASE, 3 * NUCG));
         take(L.g_part, (size_t)padded_cols(widest) * RG * 8);
@@ -296,6 +297,7 @@ int plan_orthonormalise(const Plan &pl, hipStream_t st)
 int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
 {
     PCHK(plan_orthonormalise(pl, st));
+    if (pl.gga) PCHK(launch_gga(pl, st));
     if (hartree) {
         PCHK(launch_multipole_finalize(pl, st));
         PCHK(launch_ghost(pl, st));
@@ -319,6 +321,7 @@ int plan_update(const Plan &pl, int scheme, int parity, hipStream_t st)
 int plan_energy(const Plan &pl, hipStream_t st)
 {
     PCHK(plan_orthonormalise(pl, st));
+    if (pl.gga) PCHK(launch_gga(pl, st));
     PCHK(launch_potential(pl, 1, st));
     PCHK(launch_energy_terms(pl, st));
     PCHK(launch_energy_finalize(pl, st));
@@ -549,6 +552,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     h.e_part = (double *)at(L.e_part);
     h.r_part = (double *)at(L.r_part);
     h.f_part = (double *)at(L.f_part);
+    h.gga = (double *)at(L.gga);
     h.g_part = (double *)at(L.g_part);
     h.C = (double *)at(L.C);
     h.scal = (double *)at(L.scal);
@@ -562,6 +566,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.precision = p->precision == LBKS_FP32_BULK ? 1 : 0;
     pl.no = orbital_bucket(p->n_orb);
     pl.wmode = p->ortho == LBKS_ORTHO_W;
+    pl.gga = p->xc == LBKS_XC_B88_LYP;
     pl.ntile = h.ntile;
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;
@@ -752,15 +757,25 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
     if (c->p.hartree) {
         if ((rc = enqueue_hartree_boundary(c))) return rc;
         // converge V_H for the current density: blocks of 10 sweeps until the
-        // relative residual is <= 1e-12
+        // relative residual is <= 1e-12, or until it has reached the roundoff
+        // floor of a fine grid (<= 1e-9 and no more than 10 % below its value
+        // five blocks earlier)
         const double tol = 1e-12;
+        std::vector<double> hist;
         for (int it = 0;; ++it) {
             KCHK(c, launch_residual(c->plan, c->stream));
             KCHK(c, launch_residual_finalize(c->plan, c->stream));
             double res = 0.0;
             if ((rc = read_scalar(c, SC_RES, &res))) return rc;
+            hist.push_back(res);
             if (!(res > tol)) break;
-            if (!isfinite(res) || it > 20000) return fail(c, LBKS_E_NUMERIC, "Poisson relaxation did not converge");
+            if (it >= 5 && res <= 1e-9 && res >= 0.9 * hist[it - 5]) break;
+            if (!isfinite(res) || it > 20000) {
+                char msg[128];
+                snprintf(msg, sizeof msg, "Poisson relaxation did not converge (relative residual %.3e after %d sweeps)",
+                         res, 10 * it);
+                return fail(c, LBKS_E_NUMERIC, msg);
+            }
             if ((rc = enqueue_sweeps(c, 10))) return rc;
         }
     }
@@ -1022,10 +1037,11 @@ int batch_build(lbks_batch *b)
         key.hartree = c->p.hartree;
         key.sweeps = c->p.poisson_sweeps;
         key.variant = c->plan.variant;
+        key.gga = c->plan.gga;
         BatchGroup *g = nullptr;
         for (BatchGroup &x : b->groups)
             if (x.precision == key.precision && x.no == key.no && x.wmode == key.wmode && x.scheme == key.scheme &&
-                x.hartree == key.hartree && x.sweeps == key.sweeps && x.variant == key.variant)
+                x.hartree == key.hartree && x.sweeps == key.sweeps && x.variant == key.variant && x.gga == key.gga)
                 g = &x;
         if (!g) {
             b->groups.push_back(key);
@@ -1107,6 +1123,7 @@ int batch_build(lbks_batch *b)
         pl.precision = g.precision;
         pl.no = g.no;
         pl.wmode = g.wmode;
+        pl.gga = g.gga;
         pl.n_inst = (int)g.members.size();
         pl.variant = g.variant;
     }

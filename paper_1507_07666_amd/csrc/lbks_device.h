@@ -333,6 +333,53 @@ __device__ void overlap_partial(const T (&acc)[NO], int n, double *out, int stri
     }
 }
 
+// Gradient-corrected exchange-correlation, spin-unpolarised, per volume, as a
+// function of rho and sigma = |grad rho|^2: Becke 1988 exchange, per spin
+// density n = rho/2 with x = |grad n| / n^(4/3),
+//   e_s = -C n^(4/3) - beta n^(4/3) x^2 / (1 + 6 beta x asinh x),  total 2 e_s,
+// and Lee-Yang-Parr 1988 correlation with its Laplacian terms integrated by
+// parts, f_c = f0(rho) + f1(rho) sigma,
+//   f0 = -a rho (1 + b C_F e^(-c u)) / (1 + d u),
+//   f1 = a b rho^(-5/3) e^(-c u) / (1 + d u) (3 + 7 delta) / 72,
+//   u = rho^(-1/3), delta = c u + d u / (1 + d u).
+// Returns fx, fc and the derivatives of fx + fc with respect to rho (fr) and
+// sigma (fs); all zero below the density floor.
+static __device__ void gga_eval(double rho, double sigma, double floor, double &fx, double &fc, double &fr,
+                                double &fs)
+{
+    fx = fc = fr = fs = 0.0;
+    if (!(rho >= floor) || !(rho > 0.0)) return;
+    const double PI = 3.14159265358979323846;
+    // exchange
+    const double beta = 0.0042, C = 0.75 * cbrt(6.0 / PI);
+    const double n = 0.5 * rho, n13 = cbrt(n), n43 = n * n13;
+    const double x = 0.5 * sqrt(sigma) / n43;
+    const double as = asinh(x);
+    const double q = 1.0 + 6.0 * beta * x * as;
+    const double H = x * x / q;
+    const double Hx = (2.0 * q - 6.0 * beta * x * (as + x / sqrt(1.0 + x * x))) / (q * q);   // H'(x) / x
+    fx = 2.0 * (-C * n43 - beta * n43 * H);
+    const double fx_r = -(4.0 / 3.0) * n13 * (C + beta * (H - x * x * Hx));
+    const double fx_s = -beta * Hx / (4.0 * n43);
+    // correlation
+    const double a = 0.04918, b = 0.132, c = 0.2533, d = 0.349;
+    const double CF = 0.3 * cbrt(9.0 * PI * PI * PI * PI);   // (3/10)(3 pi^2)^(2/3)
+    const double u = 1.0 / cbrt(rho);
+    const double ecu = exp(-c * u);
+    const double den = 1.0 + d * u;
+    const double num = 1.0 + b * CF * ecu;
+    const double g = num / den;
+    const double gp = (-b * CF * c * ecu * den - d * num) / (den * den);
+    const double dl = c * u + d * u / den;
+    const double A = u * u * u * u * u * ecu / den;                   // rho^(-5/3) e^(-cu) / (1 + du)
+    const double f1 = a * b * A * (3.0 + 7.0 * dl) / 72.0;
+    const double f1p = a * b * A / (216.0 * rho) * ((dl - 5.0) * (3.0 + 7.0 * dl) - 7.0 * u * (c + d / (den * den)));
+    fc = -a * rho * g + f1 * sigma;
+    const double fc_r = -a * (g - (u / 3.0) * gp) + f1p * sigma;
+    fr = fx_r + fc_r;
+    fs = fx_s + f1;
+}
+
 // Local exchange-correlation per electron (e*) and potential (v* = d(rho e*)/d rho):
 // Slater exchange; correlation of Lee-Yang-Parr at zero gradient,
 // e_c = -a (1 + b C_F exp(-c u)) / (1 + d u), u = rho^(-1/3); or Perdew-Zunger 1981.

@@ -21,6 +21,7 @@ constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
 constexpr int NUCG = 16;       // nuclei per force-kernel pass
 constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
+constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP
 
 constexpr int RG = 32;         // first-level workgroups per instance of the finalize kernels
 
@@ -65,6 +66,7 @@ struct InstDesc {
     double *r_part;            // [padded_cols(2)][ntile]
     double *f_part;            // [padded_cols(3 NUCG)][ntile]
     double *g_part;            // [padded_cols(widest partial)][RG] first-level column sums
+    double *gga;               // gradient-corrected xc: df/drho, then 2 df/dsigma D_a rho (a = x, y, z); [4][site] FP64
     const double *zr;          // nuclei: Z, x, y, z per nucleus, then the softening squared
     double *C;                 // [MAXO*MAXO] C, then [MAXO*MAXO] C* (W mode)
     double *scal;              // [SC_SIZE]
@@ -88,6 +90,7 @@ struct Plan {
     int precision = 0;    // 0 FP64, 1 FP32 bulk
     int no = 1;           // orbital bucket: 1,2,3,4,5,8,16
     bool wmode = false;
+    bool gga = false;     // gradient-corrected exchange-correlation (needs the k_gga pass)
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0;   // single-instance counts
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave occupancy
@@ -122,6 +125,7 @@ int launch_residual(const Plan &pl, hipStream_t st);
 int launch_residual_finalize(const Plan &pl, hipStream_t st);
 int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st);
 int launch_stage_orbitals(const Plan &pl, hipStream_t st);
+int launch_gga(const Plan &pl, hipStream_t st);
 int launch_force_terms(const Plan &pl, int i0, hipStream_t st);     // nuclei i0 .. i0 + NUCG - 1
 int launch_force_finalize(const Plan &pl, int i0, hipStream_t st);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);

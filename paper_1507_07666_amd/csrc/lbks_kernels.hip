@@ -389,6 +389,61 @@ __global__ __launch_bounds__(BS) void k_residual_finalize(const InstDesc *__rest
     if (threadIdx.x == 0) d.scal[SC_RES] = acc[1] > 0.0 ? sqrt(acc[0] / acc[1]) : sqrt(acc[0]);
 }
 
+// ------------------------------------------------- gradient-corrected xc
+
+// D_a rho by central differences (rho = 0 outside the box).
+template <typename T>
+__device__ __forceinline__ void grad_rho(const InstDesc &d, int s, int x, int y, int z, double (&D)[3])
+{
+    const T *r = (const T *)d.rho;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int sy = nx, sz = nx * ny;
+    const double ih2 = 1.0 / (2.0 * d.h);
+    const double xp = x + 1 < nx ? (double)r[s + 1] : 0.0, xm = x > 0 ? (double)r[s - 1] : 0.0;
+    const double yp = y + 1 < ny ? (double)r[s + sy] : 0.0, ym = y > 0 ? (double)r[s - sy] : 0.0;
+    const double zp = z + 1 < nz ? (double)r[s + sz] : 0.0, zm = z > 0 ? (double)r[s - sz] : 0.0;
+    D[0] = (xp - xm) * ih2;
+    D[1] = (yp - ym) * ih2;
+    D[2] = (zp - zm) * ih2;
+}
+
+// Per node: df/drho and 2 (df/dsigma) D_a rho of the gradient-corrected
+// functional, sigma = |D rho|^2, for the potential
+//   v_xc = df/drho - sum_a D_a [2 (df/dsigma) D_a rho],
+// the exact derivative of the discrete energy h^3 sum_r f(rho_r, sigma_r).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_gga(const InstDesc *__restrict__ descs, const int2 *__restrict__ tiles)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int s = tr.tile * BS + threadIdx.x;
+    if (s >= d.nsite) return;
+    const int x = s % d.nx, yz = s / d.nx, y = yz % d.ny, z = yz / d.ny;
+    double D[3];
+    grad_rho<T>(d, s, x, y, z, D);
+    double fx, fc, fr, fs;
+    gga_eval((double)((const T *)d.rho)[s], D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor, fx, fc, fr, fs);
+    const size_t N = (size_t)d.nsite;
+    d.gga[s] = fr;
+    d.gga[N + s] = 2.0 * fs * D[0];
+    d.gga[2 * N + s] = 2.0 * fs * D[1];
+    d.gga[3 * N + s] = 2.0 * fs * D[2];
+}
+
+// v_xc of the gradient-corrected functional at node s from the k_gga fields.
+__device__ __forceinline__ double gga_potential(const InstDesc &d, int s, int x, int y, int z)
+{
+    const size_t N = (size_t)d.nsite;
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int sy = nx, sz = nx * ny;
+    const double *gx = d.gga + N, *gy = d.gga + 2 * N, *gz = d.gga + 3 * N;
+    const double ih2 = 1.0 / (2.0 * d.h);
+    double div = ((x + 1 < nx ? gx[s + 1] : 0.0) - (x > 0 ? gx[s - 1] : 0.0)) * ih2;
+    div += ((y + 1 < ny ? gy[s + sy] : 0.0) - (y > 0 ? gy[s - sy] : 0.0)) * ih2;
+    div += ((z + 1 < nz ? gz[s + sz] : 0.0) - (z > 0 ? gz[s - sz] : 0.0)) * ih2;
+    return d.gga[s] - div;
+}
+
 // ------------------------------------------------------------- potential
 
 // V = V_ext + V_H + v_x + v_c at node s = (x, y, z), summed in that order in FP64.
@@ -397,7 +452,9 @@ __device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, 
 {
     double V = d.vext[s];
     if (d.hartree) V += d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)];
-    if (d.xc) {
+    if (d.xc == XC_GGA) {
+        V += gga_potential(d, s, x, y, z);
+    } else if (d.xc) {
         double ex, ec, vx, vc;
         xc_eval(d.xc, (double)((const T *)d.rho)[s], d.rho_floor, ex, ec, vx, vc);
         V += vx;
@@ -531,7 +588,16 @@ __global__ __launch_bounds__(BS) void k_energy_terms(const InstDesc *__restrict_
         }
         const double rho = (double)((const T *)d.rho)[s];
         double ex, ec, vx_, vc_;
-        xc_eval(d.xc, rho, d.rho_floor, ex, ec, vx_, vc_);
+        if (d.xc == XC_GGA) {
+            // energies per volume; divided back by rho so that rho * e below is f
+            double D[3], fx, fc, fr, fs;
+            grad_rho<T>(d, s, x, y, z, D);
+            gga_eval(rho, D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor, fx, fc, fr, fs);
+            ex = rho > 0.0 ? fx / rho : 0.0;
+            ec = rho > 0.0 ? fc / rho : 0.0;
+        } else {
+            xc_eval(d.xc, rho, d.rho_floor, ex, ec, vx_, vc_);
+        }
         double vh = 0.0;
         if (d.hartree) vh = d.vh[((size_t)(z + 1) * (ny + 2) + (y + 1)) * (nx + 2) + (x + 1)];
         v[2 * NO + 0] = rho * d.vext[s];
@@ -806,6 +872,15 @@ int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st)
 }
 
 
+
+int launch_gga(const Plan &pl, hipStream_t st)
+{
+    return dispatch_tt(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_gga<typename TG::T><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
+        LAUNCH_CHECK();
+    });
+}
 
 int launch_force_terms(const Plan &pl, int i0, hipStream_t st)
 {

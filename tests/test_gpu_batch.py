@@ -34,6 +34,7 @@ def mixed_systems():
         (I.h2o_batch(2)[1].scaled(24, h=0.35), dict(precision=1)),
         (I.ne_atom().scaled(20), dict(precision=1)),
         (I.atom(3, 17, h=0.35, seed=6), dict(ortho=1)),
+        (I.he_atom().scaled(18, h=0.3), dict(xc=4)),          # gradient-corrected xc: its own group
     ]
 
 

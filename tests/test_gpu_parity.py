@@ -96,6 +96,44 @@ def test_relaxation_variants_fp64(L, variant):
     s.close()
 
 
+def lda_relaxed_orbitals(system, steps=200):
+    """A smooth start for the gradient-corrected functional: the seeded orbitals
+    relaxed with the local functional on the oracle."""
+    o = O.oracle_for(system)
+    for _ in range(steps):
+        o.step()
+    psi, _ = o.state()
+    return psi.reshape((system.n_orb,) + tuple(reversed(system.dims)))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gradient_corrected_xc_matches_oracle(L, prec):
+    """Becke 88 + LYP from an LDA-relaxed start: 40 steps, state and energies."""
+    system = I.ne_atom().scaled(18, h=0.3)
+    say("gradient-corrected xc, precision", prec)
+    psi0 = lda_relaxed_orbitals(system)
+    p = L.params_for(system, init=L.LBKS_INIT_USER, xc=L.LBKS_XC_B88_LYP, precision=prec)
+    s = L.Solver(p)
+    s.set_nuclei(system.Z, system.R)
+    s.set_orbitals(psi0)
+    o = O.oracle_for(system, xc=O.XC_B88_LYP)
+    o.set_orbitals(psi0)
+    s.relax(40)
+    for _ in range(40):
+        o.step()
+    if prec == 0:
+        compare_state(s, o, 1e-10, 1e-10)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    else:
+        _, rho = s.orbitals()
+        _, rho_o = o.state()
+        assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-5 * np.linalg.norm(rho_o)
+        e, eo = s.energy(), o.energies(converge_poisson=True)
+        assert abs(e["e_x"] - eo.e_x) <= 1e-5 and abs(e["e_c"] - eo.e_c) <= 1e-5
+        assert abs(e["e_total"] - eo.e_total) <= 1e-5
+    s.close()
+
+
 def test_collapsed_scheme_matches_population_oracle(L):
     system = I.ne_atom().scaled(20)
     say("collapsed scheme")
