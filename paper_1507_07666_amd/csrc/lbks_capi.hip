@@ -515,6 +515,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     h.ntile = (h.nsite + BS - 1) / BS;
     h.ntile_ghost = (2 * (h.ny * h.nz + h.nx * h.nz + h.nx * h.ny) + BS - 1) / BS;
     h.ntile_sor = (((h.nx + 1) / 2) * h.ny * h.nz + BS - 1) / BS;
+    h.ntile_brick = bricks_of(h.nx, h.ny, h.nz);
     h.ortho = p->ortho;
     h.xc = p->xc;
     h.hartree = p->hartree;
@@ -570,6 +571,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.ntile = h.ntile;
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;
+    pl.ntile_brick = h.ntile_brick;
     pl.n_inst = 1;
     pl.variant = default_variant(pl.precision);
 
@@ -1057,25 +1059,27 @@ int batch_build(lbks_batch *b)
         return o;
     };
     struct Off {
-        size_t desc, site, ghost, sor, inst;
-        int n_site, n_ghost, n_sor;
+        size_t desc, site, ghost, sor, inst, brick;
+        int n_site, n_ghost, n_sor, n_brick;
     };
     std::vector<Off> go(b->groups.size());
     for (size_t k = 0; k < b->groups.size(); ++k) {
         const BatchGroup &g = b->groups[k];
         Off &o = go[k];
-        o.n_site = o.n_ghost = o.n_sor = 0;
+        o.n_site = o.n_ghost = o.n_sor = o.n_brick = 0;
         for (int i : g.members) {
             const InstDesc &h = b->members[i]->h;
             o.n_site += h.ntile;
             o.n_ghost += h.ntile_ghost;
             o.n_sor += h.ntile_sor;
+            o.n_brick += h.ntile_brick;
         }
         o.desc = take(sizeof(InstDesc) * g.members.size());
         o.site = take(sizeof(int2) * o.n_site);
         o.ghost = take(sizeof(int2) * o.n_ghost);
         o.sor = take(sizeof(int2) * o.n_sor);
         o.inst = take(sizeof(int) * g.members.size());
+        o.brick = take(sizeof(int2) * o.n_brick);
     }
     const size_t gather_off = take(sizeof(double) * GATHER_W * std::max(m, 1));
     const size_t scal_off = take(sizeof(double *) * std::max(m, 1));
@@ -1098,7 +1102,8 @@ int batch_build(lbks_batch *b)
         int2 *tg = (int2 *)(host.data() + o.ghost);
         int2 *tr = (int2 *)(host.data() + o.sor);
         int *ti = (int *)(host.data() + o.inst);
-        int ns = 0, ng = 0, nr = 0;
+        int2 *tb = (int2 *)(host.data() + o.brick);
+        int ns = 0, ng = 0, nr = 0, nb = 0;
         for (size_t q = 0; q < g.members.size(); ++q) {
             const lbks_ctx *c = b->members[g.members[q]];
             InstDesc d = c->h;
@@ -1107,6 +1112,7 @@ int batch_build(lbks_batch *b)
             for (int t = 0; t < d.ntile; ++t) ts[ns++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_ghost; ++t) tg[ng++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_sor; ++t) tr[nr++] = make_int2((int)q, t);
+            for (int t = 0; t < d.ntile_brick; ++t) tb[nb++] = make_int2((int)q, t);
             ti[q] = (int)q;
         }
         Plan &pl = g.plan;
@@ -1120,6 +1126,8 @@ int batch_build(lbks_batch *b)
         pl.tt.n_sor = o.n_sor;
         pl.tt.inst = (const int *)(base + o.inst);
         pl.tt.n_inst = (int)g.members.size();
+        pl.tt.brick = (const int2 *)(base + o.brick);
+        pl.tt.n_brick = o.n_brick;
         pl.precision = g.precision;
         pl.no = g.no;
         pl.wmode = g.wmode;

@@ -153,6 +153,109 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
     overlap_partial_v<T, NO, V>(acc, n, d.s_part + tr.tile, d.ntile);
 }
 
+// The same omega = 1 update (Gram-Schmidt mode, psi* = psi_hat) with the fields
+// staged in LDS: a workgroup owns a brick of BX x BY nodes in x, y and marches
+// over BZ planes in z, keeping three planes of psi_hat_j and V with a one-node
+// halo in a ring (the plane after next is fetched into registers while a plane
+// is computed), so each field value is read from memory about once instead of
+// once per neighbour.  The terms are added in the same order as in k_collapsed;
+// terms from outside the box are exact zeros there and skipped here, so the new
+// orbitals are the same.  Only the orbitals are written; the overlap partials
+// come from k_overlap_psi.
+template <typename T, int NO>
+__global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restrict__ descs,
+                                                        const int2 *__restrict__ bricks)
+{
+    constexpr int PX = BX + 2, PY = BY + 2, PL = PX * PY;
+    constexpr int NL = (PL + BS - 1) / BS;         // plane positions per thread
+    __shared__ T lds[NO + 1][3][PL];              // psi_hat_0 .. psi_hat_{NO-1}, V; three planes
+    const TileRef tr = resolve(bricks);
+    const InstDesc &d = descs[tr.inst];
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int gx = (nx + BX - 1) / BX, gy = (ny + BY - 1) / BY;
+    const int b = tr.tile;
+    const int x0 = (b % gx) * BX, y0 = ((b / gx) % gy) * BY, z0 = (b / (gx * gy)) * BZ;
+    const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
+    const int x = x0 + tx, y = y0 + ty;
+    const size_t N = (size_t)d.nsite;
+    const T *__restrict__ ph = (const T *)d.psihat;
+    const T *__restrict__ Vp = (const T *)d.V;
+    T *psi = (T *)d.psi;
+    // the weights by speed class (|v_p|^2 = 0, 1, 2: velocities 0, 1, 7), and dt chi
+    // formed as the node kernel forms it
+    T cxi[3], cdc[3];
+    {
+        const T dt = (T)d.dt;
+        const int rep[3] = {0, 1, 7};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cxi[c] = (T)d.xi[rep[c]];
+            cdc[c] = dt * (T)d.chi[rep[c]];
+        }
+    }
+    // one plane (zero outside the box) into registers, then into a ring slot
+    T pre[NL][NO + 1];
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int i = (int)threadIdx.x + q * BS;
+            const int lx = x0 - 1 + i % PX, ly = y0 - 1 + i / PX;
+            const bool in = i < PL && z >= 0 && z < nz && lx >= 0 && lx < nx && ly >= 0 && ly < ny;
+            const size_t g = in ? ((size_t)z * ny + ly) * nx + lx : 0;
+#pragma unroll
+            for (int j = 0; j < NO; ++j) pre[q][j] = in ? ph[(size_t)j * N + g] : (T)0;
+            pre[q][NO] = in ? Vp[g] : (T)0;
+        }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int i = (int)threadIdx.x + q * BS;
+            if (i < PL)
+#pragma unroll
+                for (int j = 0; j <= NO; ++j) lds[j][slot][i] = pre[q][j];
+        }
+    };
+    fetch(z0 - 1);
+    store(0);
+    fetch(z0);
+    store(1);
+    fetch(z0 + 1);
+    store(2);
+    fetch(z0 + 2);
+    __syncthreads();
+    for (int k = 0; k < BZ; ++k) {
+        const int z = z0 + k;
+        if (z >= nz) break;                         // the same for the whole workgroup
+        if (x < nx && y < ny) {
+            T acc[NO];
+#pragma unroll
+            for (int j = 0; j < NO; ++j) acc[j] = (T)0;
+            // a departure node outside the box holds zeros in LDS, so its term adds
+            // exactly nothing (no per-direction test is needed)
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const int vx = VX(p), vy = VY(p), vz = VZ(p);
+                const int c = vx * vx + vy * vy + vz * vz;
+                const int slot = (k + 1 - vz + 3) % 3;
+                const int li = (ty + 1 - vy) * PX + (tx + 1 - vx);
+                const T dp = cdc[c] * lds[NO][slot][li];
+#pragma unroll
+                for (int j = 0; j < NO; ++j) acc[j] += (cxi[c] - dp) * lds[j][slot][li];
+            }
+            const size_t s = ((size_t)z * ny + y) * nx + x;
+#pragma unroll
+            for (int j = 0; j < NO; ++j) psi[(size_t)j * N + s] = acc[j];
+        }
+        __syncthreads();                            // slot k % 3 (plane z - 1) is no longer read
+        if (k + 1 < BZ) {
+            store(k % 3);                           // plane z + 2, fetched one plane ago
+            fetch(z + 3);                           // in flight while plane z + 1 is computed
+        }
+        __syncthreads();
+    }
+}
+
 template <int V>
 static int launch_stream_collide_v(const Plan &pl, int parity, hipStream_t st)
 {
@@ -183,8 +286,26 @@ int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
     }
 }
 
+// Gram-Schmidt mode with at most five orbitals: the LDS-staged brick update, then
+// the overlap partials of the new orbitals; otherwise the node-per-thread update
+// with the fused overlap partials, in the autotuned variant.
+bool collapsed_uses_bricks(const Plan &pl) { return !pl.wmode && pl.no <= 5; }
+
 int launch_collapsed_update(const Plan &pl, hipStream_t st)
 {
+    if (collapsed_uses_bricks(pl)) {
+        const int e = dispatch_tn(pl, [&](auto tg) {
+            using TG = decltype(tg);
+            if constexpr (TG::NO <= 5) {
+                k_collapsed_brick<typename TG::T, TG::NO><<<grid_brick(pl), BS, 0, st>>>(pl.d_desc, pl.tt.brick);
+                return (int)hipGetLastError();
+            } else {
+                return (int)hipErrorInvalidValue;
+            }
+        });
+        if (e) return e;
+        return launch_overlap_psi(pl, st);
+    }
     switch (pl.variant & 3) {
     case 0: return launch_collapsed_v<0>(pl, st);
     case 1: return launch_collapsed_v<1>(pl, st);

@@ -19,6 +19,12 @@ constexpr int MAXO = 16;       // orbital capacity of the descriptor
 constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
+constexpr int BX = 32, BY = 8, BZ = 4;   // brick of the LDS-staged omega = 1 update (BX * BY = BS)
+
+__host__ __device__ constexpr int bricks_of(int nx, int ny, int nz)
+{
+    return ((nx + BX - 1) / BX) * ((ny + BY - 1) / BY) * ((nz + BZ - 1) / BZ);
+}
 constexpr int NUCG = 16;       // nuclei per force-kernel pass
 constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
 constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP
@@ -44,6 +50,7 @@ struct InstDesc {
     int ntile;                 // site tiles of BS nodes
     int ntile_ghost;           // tiles over the six ghost faces
     int ntile_sor;             // tiles over one colour of the SOR sweep
+    int ntile_brick;           // BX x BY x BZ bricks of the omega = 1 field update
     int ortho, xc, hartree, precision;
     int scheme;
     int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
@@ -79,6 +86,7 @@ struct TileTables {
     const int2 *ghost = nullptr;  int n_ghost = 0;
     const int2 *sor = nullptr;    int n_sor = 0;
     const int *inst = nullptr;    int n_inst = 0;   // instance list for per-instance kernels
+    const int2 *brick = nullptr;  int n_brick = 0;
 };
 
 // Launch plan of one kernel family: descriptor array on the device, tile
@@ -91,7 +99,7 @@ struct Plan {
     int no = 1;           // orbital bucket: 1,2,3,4,5,8,16
     bool wmode = false;
     bool gga = false;     // gradient-corrected exchange-correlation (needs the k_gga pass)
-    int ntile = 0, ntile_ghost = 0, ntile_sor = 0;   // single-instance counts
+    int ntile = 0, ntile_ghost = 0, ntile_sor = 0, ntile_brick = 0;   // single-instance counts
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave occupancy
 };

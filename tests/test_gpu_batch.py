@@ -35,6 +35,8 @@ def mixed_systems():
         (I.ne_atom().scaled(20), dict(precision=1)),
         (I.atom(3, 17, h=0.35, seed=6), dict(ortho=1)),
         (I.he_atom().scaled(18, h=0.3), dict(xc=4)),          # gradient-corrected xc: its own group
+        (I.ne_atom().scaled(21, h=0.3), dict(scheme=1)),      # omega = 1 field update (LDS bricks)
+        (I.atom(6, 19, h=0.32, seed=7), dict(scheme=1, precision=1)),
     ]
 
 
