@@ -572,6 +572,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;
     pl.ntile_brick = h.ntile_brick;
+    pl.brick_partials = brick_partials(h.ntile, h.ntile_brick);
     pl.n_inst = 1;
     pl.variant = default_variant(pl.precision);
 
@@ -1104,6 +1105,7 @@ int batch_build(lbks_batch *b)
         int *ti = (int *)(host.data() + o.inst);
         int2 *tb = (int2 *)(host.data() + o.brick);
         int ns = 0, ng = 0, nr = 0, nb = 0;
+        bool all_brick = true;
         for (size_t q = 0; q < g.members.size(); ++q) {
             const lbks_ctx *c = b->members[g.members[q]];
             InstDesc d = c->h;
@@ -1113,6 +1115,7 @@ int batch_build(lbks_batch *b)
             for (int t = 0; t < d.ntile_ghost; ++t) tg[ng++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_sor; ++t) tr[nr++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_brick; ++t) tb[nb++] = make_int2((int)q, t);
+            all_brick = all_brick && brick_partials(d.ntile, d.ntile_brick);
             ti[q] = (int)q;
         }
         Plan &pl = g.plan;
@@ -1128,6 +1131,7 @@ int batch_build(lbks_batch *b)
         pl.tt.n_inst = (int)g.members.size();
         pl.tt.brick = (const int2 *)(base + o.brick);
         pl.tt.n_brick = o.n_brick;
+        pl.brick_partials = all_brick;
         pl.precision = g.precision;
         pl.no = g.no;
         pl.wmode = g.wmode;

@@ -39,7 +39,7 @@ template <typename T, int NO, bool W, int V>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V>(), 8))) void k_stream_collide(const InstDesc *__restrict__ descs,
                                                        const int2 *__restrict__ tiles, int parity)
 {
-    const TileRef tr = resolve(tiles);
+    const TileRef tr = resolve<false>(tiles);
     const InstDesc &d = descs[tr.inst];
     const int n = orbitals<NO>(d);
     const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -160,8 +160,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
 // is computed), so each field value is read from memory about once instead of
 // once per neighbour.  The terms are added in the same order as in k_collapsed;
 // terms from outside the box are exact zeros there and skipped here, so the new
-// orbitals are the same.  Only the orbitals are written; the overlap partials
-// come from k_overlap_psi.
+// orbitals are the same.  The overlap partial of the brick (psi_j psi_k summed
+// over its nodes in FP64, the planes in order) goes to tile slot b when the
+// instance has no more bricks than node tiles (slots from the brick count on are
+// zeroed by the bricks in turn); otherwise k_overlap_psi writes the partials.
 template <typename T, int NO>
 __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restrict__ descs,
                                                         const int2 *__restrict__ bricks)
@@ -224,6 +226,9 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
     store(2);
     fetch(z0 + 2);
     __syncthreads();
+    double prod[NO * (NO + 1) / 2];
+#pragma unroll
+    for (int q = 0; q < NO * (NO + 1) / 2; ++q) prod[q] = 0.0;
     for (int k = 0; k < BZ; ++k) {
         const int z = z0 + k;
         if (z >= nz) break;                         // the same for the whole workgroup
@@ -246,6 +251,11 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
             const size_t s = ((size_t)z * ny + y) * nx + x;
 #pragma unroll
             for (int j = 0; j < NO; ++j) psi[(size_t)j * N + s] = acc[j];
+            int q = 0;
+#pragma unroll
+            for (int j = 0; j < NO; ++j)
+#pragma unroll
+                for (int kk = 0; kk <= j; ++kk) prod[q++] += (double)acc[j] * (double)acc[kk];
         }
         __syncthreads();                            // slot k % 3 (plane z - 1) is no longer read
         if (k + 1 < BZ) {
@@ -253,6 +263,12 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
             fetch(z + 3);                           // in flight while plane z + 1 is computed
         }
         __syncthreads();
+    }
+    if (brick_partials(d.ntile, d.ntile_brick)) {   // uniform per workgroup
+        const int np = NO * (NO + 1) / 2;
+        block_sum_store(prod, np, d.s_part + b, d.ntile);
+        if ((int)threadIdx.x < np)
+            for (int t = d.ntile_brick + b; t < d.ntile; t += d.ntile_brick) d.s_part[(size_t)threadIdx.x * d.ntile + t] = 0.0;
     }
 }
 
@@ -286,8 +302,8 @@ int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
     }
 }
 
-// Gram-Schmidt mode with at most five orbitals: the LDS-staged brick update, then
-// the overlap partials of the new orbitals; otherwise the node-per-thread update
+// Gram-Schmidt mode with at most five orbitals: the LDS-staged brick update (with
+// the overlap partials, or followed by them); otherwise the node-per-thread update
 // with the fused overlap partials, in the autotuned variant.
 bool collapsed_uses_bricks(const Plan &pl) { return !pl.wmode && pl.no <= 5; }
 
@@ -304,7 +320,7 @@ int launch_collapsed_update(const Plan &pl, hipStream_t st)
             }
         });
         if (e) return e;
-        return launch_overlap_psi(pl, st);
+        return pl.brick_partials ? 0 : launch_overlap_psi(pl, st, true);
     }
     switch (pl.variant & 3) {
     case 0: return launch_collapsed_v<0>(pl, st);

@@ -48,9 +48,14 @@ struct TileRef {
     int inst, tile;
 };
 
+// REMAP = false keeps the dispatch order: the workgroups in flight then cover one
+// window of tiles, so the population kernel's 190 streams touch one region of
+// each plane at a time (fewer DRAM rows open), and the neighbour-plane field reads
+// that leave an XCD's L2 are served by the shared last-level cache.
+template <bool REMAP = true>
 __device__ __forceinline__ TileRef resolve(const int2 *table)
 {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     if (table) {
         const int2 t = table[b];
         return {t.x, t.y};

@@ -19,12 +19,16 @@ constexpr int MAXO = 16;       // orbital capacity of the descriptor
 constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
-constexpr int BX = 32, BY = 8, BZ = 4;   // brick of the LDS-staged omega = 1 update (BX * BY = BS)
+constexpr int BX = 32, BY = 8, BZ = 2;   // brick of the LDS-staged omega = 1 update (BX * BY = BS)
 
 __host__ __device__ constexpr int bricks_of(int nx, int ny, int nz)
 {
     return ((nx + BX - 1) / BX) * ((ny + BY - 1) / BY) * ((nz + BZ - 1) / BZ);
 }
+// The brick update writes the overlap partials itself (brick b into tile slot b,
+// the slots past the last brick zero) when an instance has no more bricks than
+// node tiles; otherwise a separate pass over the node tiles writes them.
+__host__ __device__ constexpr bool brick_partials(int ntile, int nbrick) { return nbrick <= ntile; }
 constexpr int NUCG = 16;       // nuclei per force-kernel pass
 constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
 constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP
@@ -102,6 +106,7 @@ struct Plan {
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0, ntile_brick = 0;   // single-instance counts
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave occupancy
+    bool brick_partials = true;   // every instance gets its overlap partials from the brick update
 };
 
 // Default update-kernel variant per precision (measured on MI355X): FP64 keeps the
@@ -117,7 +122,7 @@ int launch_init_psi(const Plan &pl, int mode, double sigma, double noise, uint64
 int launch_psi_from_stage(const Plan &pl, hipStream_t st);
 int launch_equilibrium(const Plan &pl, int parity, hipStream_t st);
 int launch_moment(const Plan &pl, int parity, hipStream_t st);
-int launch_overlap_psi(const Plan &pl, hipStream_t st);
+int launch_overlap_psi(const Plan &pl, hipStream_t st, bool skip_brick = false);
 int launch_overlap_finalize(const Plan &pl, hipStream_t st);
 int launch_orthonormalise(const Plan &pl, hipStream_t st);
 int launch_multipole_finalize(const Plan &pl, hipStream_t st);

@@ -120,13 +120,15 @@ __global__ __launch_bounds__(BS) void k_moment(const InstDesc *__restrict__ desc
     overlap_partial<T, NO>(acc, n, d.s_part + tr.tile, d.ntile);
 }
 
-// Overlap partials of the orbital state itself (collapsed scheme).
+// Overlap partials of the orbital state itself.  With skip_brick, instances whose
+// partials the brick update has already written are left alone.
 template <typename T, int NO>
 __global__ __launch_bounds__(BS) void k_overlap_psi(const InstDesc *__restrict__ descs,
-                                                    const int2 *__restrict__ tiles)
+                                                    const int2 *__restrict__ tiles, int skip_brick)
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
+    if (skip_brick && brick_partials(d.ntile, d.ntile_brick)) return;   // uniform per workgroup
     const int n = orbitals<NO>(d);
     const int s = tr.tile * BS + threadIdx.x;
     const T *psi = (const T *)d.psi;
@@ -784,11 +786,11 @@ int launch_moment(const Plan &pl, int parity, hipStream_t st)
     });
 }
 
-int launch_overlap_psi(const Plan &pl, hipStream_t st)
+int launch_overlap_psi(const Plan &pl, hipStream_t st, bool skip_brick)
 {
     return dispatch_tn(pl, [&](auto tg) {
         using TG = decltype(tg);
-        k_overlap_psi<typename TG::T, TG::NO><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
+        k_overlap_psi<typename TG::T, TG::NO><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, skip_brick ? 1 : 0);
         LAUNCH_CHECK();
     });
 }

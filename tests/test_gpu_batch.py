@@ -36,6 +36,7 @@ def mixed_systems():
         (I.atom(3, 17, h=0.35, seed=6), dict(ortho=1)),
         (I.he_atom().scaled(18, h=0.3), dict(xc=4)),          # gradient-corrected xc: its own group
         (I.ne_atom().scaled(21, h=0.3), dict(scheme=1)),      # omega = 1 field update (LDS bricks)
+        (I.ne_atom().scaled(19, h=0.3), dict(scheme=1)),      # same group; more bricks than tiles
         (I.atom(6, 19, h=0.32, seed=7), dict(scheme=1, precision=1)),
     ]
 
@@ -56,13 +57,16 @@ def test_batch_equals_alone_fixed_steps(L):
     systems = mixed_systems()
     b = L.Batch()
     members = [b.add_system(sy, **kw) for sy, kw in systems]
-    variants = [0, 1, 2, 3, 3, 2]
+    variants = [0, 1, 2, 3, 3, 2] + [None] * (len(systems) - 6)
     for m, v in zip(members, variants):
-        m.set_variant(v)
+        if v is not None:
+            m.set_variant(v)
     st, steps = b.relax(25, dE_tol=0.0, check_every=10)
     assert steps == [25] * len(systems)
     assert all(x == L.LBKS_NOT_CONVERGED for x in st)
+    assert len(variants) == len(members) == len(systems)
     for (sy, kw), s, v in zip(systems, members, variants):
+        say("member", sy.name, kw)
         psi, rho = s.orbitals()
         _, psi_a, rho_a, _ = alone(L, sy, kw, 25, variant=v)
         assert np.array_equal(psi, psi_a) and np.array_equal(rho, rho_a), sy.name
