@@ -277,7 +277,12 @@ def main():
         solver.set_variant(args.variant)
     if args.warmup:
         solver.relax(args.warmup)
-    if args.no_autotune or args.variant is not None:
+    # the LDS-staged field update (collapsed scheme, Gram-Schmidt, at most five
+    # orbitals) has a single form: nothing to tune
+    bricks = scheme == lbks.LBKS_SCHEME_COLLAPSED and system.n_orb <= 5
+    if bricks:
+        variant, tune_ms = None, None
+    elif args.no_autotune or args.variant is not None:
         variant, tune_ms = solver.variant(), None
     else:
         variant, tune_ms = solver.autotune(reps=5, force=True)
@@ -321,10 +326,10 @@ def main():
         avg_s = k1_ms / k1_n * 1e-3
         alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme)
         ach = alg / avg_s / 1e9
-        tkey = f"{args.workload}_{args.precision}_v{variant}" if scheme == 0 else None
+        tkey = f"{args.workload}_{args.precision}_" + (f"v{variant}" if scheme == 0 else "collapsed" if bricks else "")
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(tkey) if tkey else None,
-                           "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed",
+                           "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed_brick" if bricks else "k_collapsed",
                            "avg_us": avg_s * 1e6, "launches": k1_n, "alg_bytes_per_launch": alg}
         # the same bytes against what a plain copy kernel reaches on this GPU
         cp = copy_calibration(678 << 20, 20)

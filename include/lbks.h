@@ -244,11 +244,15 @@ size_t lbks_estimate_bytes(const lbks_params *p);
 int lbks_set_timing(lbks_ctx *ctx, int32_t enable);
 int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
-/* Update-kernel variants: bit 0 computes the per-workgroup overlap partial
+/* Update-kernel variants 0..7: bit 0 computes the per-workgroup overlap partial
  * S = Phi^T Phi on the matrix cores (V_MFMA_F64_16X16X4F64) instead of a wave
- * butterfly, bit 1 compiles the kernel for 8 waves per SIMD.  Every variant
- * computes the same arithmetic; only the overlap's summation order differs.
- * Defaults: 0 for FP64, 3 for FP32. */
+ * butterfly, bit 1 compiles the kernel for 8 waves per SIMD, bit 2 runs the
+ * workgroups in dispatch order instead of giving each XCD one contiguous range
+ * of tiles.  Every variant computes the same arithmetic; only the overlap's
+ * summation order differs with bit 0 (bit 2 changes nothing in the results).
+ * The LDS-staged omega = 1 update (Gram-Schmidt, at most five orbitals) has one
+ * form and ignores the variant.  Defaults: 4 for FP64, 3 for FP32.
+ * lbks_set_variant: LBKS_E_INVAL outside 0..7. */
 int lbks_set_variant(lbks_ctx *ctx, int32_t variant);
 int lbks_get_variant(const lbks_ctx *ctx);
 
@@ -256,7 +260,7 @@ int lbks_get_variant(const lbks_ctx *ctx);
  * and keep the fastest (state unchanged).  Choices are cached per (precision,
  * orbital bucket, orthogonalisation, scheme, node count) for the process; with
  * force = 0 a cached choice is reused without timing.  chosen (may be NULL)
- * receives the variant, avg_ms (NULL, or 4 doubles) the per-launch times
+ * receives the variant, avg_ms (NULL, or 8 doubles) the per-launch times
  * (-1 when the cache answered).  LBKS_E_STATE if no potential is set. */
 int lbks_autotune(lbks_ctx *ctx, int32_t reps, int32_t force, int32_t *chosen, double *avg_ms);
 

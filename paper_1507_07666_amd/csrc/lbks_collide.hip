@@ -15,7 +15,8 @@ namespace lbks {
 // g_jp = sum_{l<=j} f_lp C_lj, and zero when r - v_p is outside the box.  The new
 // moment psi_j = sum_p f_jp and the overlap partials psi_j psi_k are fused.
 // Variant bits: 1 = overlap partial on the matrix cores (else wave butterfly),
-// 2 = ask the compiler for 8 waves per SIMD (else its own register budget).
+// 2 = ask the compiler for 8 waves per SIMD (else its own register budget),
+// 4 = workgroups in dispatch order (else the XCD remap); bit 4 is a kernel argument.
 template <int V>
 __device__ __forceinline__ constexpr int waves_hint() { return (V & 2) ? 8 : 1; }
 
@@ -37,9 +38,9 @@ __device__ __forceinline__ void overlap_partial_v(const T (&acc)[NO], int n, dou
 
 template <typename T, int NO, bool W, int V>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V>(), 8))) void k_stream_collide(const InstDesc *__restrict__ descs,
-                                                       const int2 *__restrict__ tiles, int parity)
+                                                       const int2 *__restrict__ tiles, int parity, int linear)
 {
-    const TileRef tr = resolve<false>(tiles);
+    const TileRef tr = resolve(tiles, linear);
     const InstDesc &d = descs[tr.inst];
     const int n = orbitals<NO>(d);
     const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -109,9 +110,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
 // exactly the moment of the population update at omega = 1.
 template <typename T, int NO, bool W, int V>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V>(), 8))) void k_collapsed(const InstDesc *__restrict__ descs,
-                                                  const int2 *__restrict__ tiles)
+                                                  const int2 *__restrict__ tiles, int linear)
 {
-    const TileRef tr = resolve(tiles);
+    const TileRef tr = resolve(tiles, linear);
     const InstDesc &d = descs[tr.inst];
     const int n = orbitals<NO>(d);
     const int nx = d.nx, ny = d.ny, nz = d.nz;
@@ -277,7 +278,8 @@ static int launch_stream_collide_v(const Plan &pl, int parity, hipStream_t st)
 {
     return dispatch_tnw(pl, [&](auto tg) {
         using TG = decltype(tg);
-        k_stream_collide<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, parity);
+        k_stream_collide<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, parity,
+                                                                                       (pl.variant >> 2) & 1);
         LAUNCH_CHECK();
     });
 }
@@ -287,7 +289,7 @@ static int launch_collapsed_v(const Plan &pl, hipStream_t st)
 {
     return dispatch_tnw(pl, [&](auto tg) {
         using TG = decltype(tg);
-        k_collapsed<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
+        k_collapsed<typename TG::T, TG::NO, TG::W, V><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, (pl.variant >> 2) & 1);
         LAUNCH_CHECK();
     });
 }

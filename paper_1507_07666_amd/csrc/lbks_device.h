@@ -48,14 +48,14 @@ struct TileRef {
     int inst, tile;
 };
 
-// REMAP = false keeps the dispatch order: the workgroups in flight then cover one
-// window of tiles, so the population kernel's 190 streams touch one region of
-// each plane at a time (fewer DRAM rows open), and the neighbour-plane field reads
-// that leave an XCD's L2 are served by the shared last-level cache.
-template <bool REMAP = true>
-__device__ __forceinline__ TileRef resolve(const int2 *table)
+// linear = 1 keeps the dispatch order instead of the remap (update-kernel variant
+// bit 2): the workgroups in flight then cover one window of tiles, so the many
+// population streams each touch one region at a time; the neighbour-plane field
+// reads are then split over the XCDs' L2s.  Which order is faster depends on the
+// grid, so the autotuner decides.
+__device__ __forceinline__ TileRef resolve(const int2 *table, int linear = 0)
 {
-    const int b = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int b = linear ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     if (table) {
         const int2 t = table[b];
         return {t.x, t.y};

@@ -105,15 +105,16 @@ struct Plan {
     bool gga = false;     // gradient-corrected exchange-correlation (needs the k_gga pass)
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0, ntile_brick = 0;   // single-instance counts
     int n_inst = 1;
-    int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave occupancy
+    int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave
+                          // occupancy, bit 2 workgroups in dispatch order
     bool brick_partials = true;   // every instance gets its overlap partials from the brick update
 };
 
 // Default update-kernel variant per precision (measured on MI355X): FP64 keeps the
-// wave-butterfly overlap at the compiler's occupancy, FP32 takes the matrix-core
-// overlap at 8 waves per SIMD.
-inline int default_variant(int precision) { return precision ? 3 : 0; }
-constexpr int N_VARIANTS = 4;
+// wave-butterfly overlap at the compiler's occupancy with workgroups in dispatch
+// order, FP32 takes the matrix-core overlap at 8 waves per SIMD with the XCD remap.
+inline int default_variant(int precision) { return precision ? 3 : 4; }
+constexpr int N_VARIANTS = 8;
 
 int orbital_bucket(int n_orb);
 

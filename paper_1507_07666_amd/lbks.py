@@ -315,7 +315,7 @@ class Solver:
         """Pick the fastest update-kernel variant on the current state; returns
         (variant, per-variant ms or None when the process cache answered)."""
         ch = c_int32()
-        ms = (c_double * 4)()
+        ms = (c_double * 8)()
         _check(self.ctx, load().lbks_autotune(self.ctx, int(reps), 1 if force else 0, ctypes.byref(ch), ms))
         times = list(ms)
         return ch.value, (None if times[0] < 0 else times)

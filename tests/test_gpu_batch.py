@@ -57,7 +57,7 @@ def test_batch_equals_alone_fixed_steps(L):
     systems = mixed_systems()
     b = L.Batch()
     members = [b.add_system(sy, **kw) for sy, kw in systems]
-    variants = [0, 1, 2, 3, 3, 2] + [None] * (len(systems) - 6)
+    variants = [0, 5, 2, 7, 3, 6] + [None] * (len(systems) - 6)
     for m, v in zip(members, variants):
         if v is not None:
             m.set_variant(v)
