@@ -244,8 +244,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(a solve shards by z-slabs in principle; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent solves would be spread over GPUs, and one large solve split "
+              "into z-slabs).", file=sys.stderr)
         sys.exit(2)
 
     import torch
