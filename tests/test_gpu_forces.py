@@ -63,6 +63,11 @@ def systems(case):
         return s
     if case == "h20":
         return h_cluster()
+    if case == "h64":
+        # the nuclei capacity (64: four passes of 16), 32 electrons in 16 orbitals
+        s = h_cluster(count=64, n=22, h=0.4, seed=23)
+        s.name, s.n_elec, s.n_orb = "H64+32", 32, 16
+        return s
     raise KeyError(case)
 
 
@@ -74,7 +79,7 @@ def pair(L, system, **kw):
     return s, o
 
 
-@pytest.mark.parametrize("case", ["h2", "h2o", "h2o_fp32", "h2o_collapsed", "h20"])
+@pytest.mark.parametrize("case", ["h2", "h2o", "h2o_fp32", "h2o_collapsed", "h20", "h64"])
 def test_forces_match_oracle(L, case):
     system = systems(case)
     kw = {}
@@ -84,7 +89,7 @@ def test_forces_match_oracle(L, case):
         kw["scheme"] = L.LBKS_SCHEME_COLLAPSED
     say("forces", case, len(system.Z), "nuclei")
     s, o = pair(L, system, **kw)
-    steps = 10 if case == "h20" else 25
+    steps = 10 if case in ("h20", "h64") else 25
     s.relax(steps)
     for _ in range(steps):
         o.step()

@@ -149,6 +149,52 @@ def test_collapsed_scheme_matches_population_oracle(L, n):
     s.close()
 
 
+def non_cubic(system, dims=(30, 22, 13)):
+    s = system.scaled(dims[0])
+    s.dims = tuple(dims)
+    return s
+
+
+@pytest.mark.parametrize("case", ["gs", "w", "collapsed", "fp32"])
+def test_non_cubic_grid_matches_oracle(L, case):
+    """Three different edge lengths, each ragged against the 256-node tiles, the
+    32 x 8 x 2 bricks and the SOR colouring: 30 x 22 x 13 nodes (33.5 tiles; the
+    collapsed bricks write the overlap partials)."""
+    system = non_cubic(I.ne_atom())
+    kw = {"gs": {}, "w": dict(ortho=1), "collapsed": dict(scheme=L.LBKS_SCHEME_COLLAPSED),
+          "fp32": dict(precision=L.LBKS_FP32_BULK)}[case]
+    say("non-cubic", case, system.dims)
+    s, o = make_pair(L, system, **kw)
+    s.relax(30)
+    for _ in range(30):
+        o.step()
+    if case == "fp32":
+        _, rho = s.orbitals()
+        _, rho_o = o.state()
+        assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-5 * np.linalg.norm(rho_o)
+        assert abs(s.energy()["e_total"] - o.energies(converge_poisson=True).e_total) <= 1e-5
+    else:
+        compare_state(s, o, 1e-10, 1e-10)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("Z,kw", [(12, {}), (12, dict(scheme=1)), (32, {}), (32, dict(ortho=1))],
+                         ids=["6orb", "6orb_collapsed", "16orb", "16orb_w"])
+def test_orbital_buckets_8_and_16_match_oracle(L, Z, kw):
+    """Orbital counts above five run the kernels built for 8 or 16 orbitals, with the
+    count read at run time (6 of 8, and the full 16)."""
+    system = I.atom(Z, 16, h=0.3, softening=0.3, seed=11)
+    say("bucket", Z, kw, system.n_orb, "orbitals")
+    s, o = make_pair(L, system, **kw)
+    s.relax(20)
+    for _ in range(20):
+        o.step()
+    compare_state(s, o, 1e-10, 1e-10)
+    compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
 def test_device_initial_orbitals_match_seeded_generator(L):
     """SplitMix64 start generated on the device equals the inputs module's."""
     for system in (I.he_atom().scaled(12), I.ne_atom().scaled(12)):
@@ -239,6 +285,9 @@ def test_error_paths(L):
     assert ei.value.code == L.LBKS_E_INVAL
     with pytest.raises(L.LbksError) as ei:
         s.set_nuclei([-1.0], [[0.0, 0.0, 0.0]])
+    assert ei.value.code == L.LBKS_E_INVAL
+    with pytest.raises(L.LbksError) as ei:          # one more than LBKS_MAX_NUC
+        s.set_nuclei([0.1] * 65, [[0.01 * k, 0.0, 0.0] for k in range(65)])
     assert ei.value.code == L.LBKS_E_INVAL
     s.set_nuclei(system.Z, system.R)
     bad = system.psi0()
