@@ -61,19 +61,32 @@ def measured_traffic(key):
     return d.get(key)
 
 
-def cpu_baseline(system, steps, threads):
-    """The FP64 CPU oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_baseline(system, steps, steps_1t):
+    """The FP64 CPU oracle, as it stands, on a bounded sample of the same workload:
+    `steps` steps on every thread the OpenMP runtime offers, then `steps_1t` steps on
+    one thread (the oracle's results do not depend on the thread count)."""
     from oracle import oracle as O
+    threads = O.max_threads()
     o = O.oracle_for(system)
     o.step()                      # warm caches / first-touch
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        o.step()
-    dt = time.perf_counter() - t0
-    return {"value": system.n_orb * system.n_sites * steps / dt, "unit": "orbital-site updates/s",
-            "cores": threads, "kind": "oracle",
+
+    def rate(k):
+        t0 = time.perf_counter()
+        for _ in range(k):
+            o.step()
+        return system.n_orb * system.n_sites * k / (time.perf_counter() - t0)
+
+    v = rate(steps)
+    O.set_threads(1)
+    try:
+        v1 = rate(steps_1t)
+    finally:
+        O.set_threads(threads)
+    return {"value": v, "unit": "orbital-site updates/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": v1,
             "sample": f"{steps} oracle steps of the same workload ({system.name} "
-                      f"{system.dims[0]}^3, {system.n_orb} orbitals, FP64) after 1 untimed step"}
+                      f"{system.dims[0]}^3, {system.n_orb} orbitals, FP64) after 1 untimed step on "
+                      f"{threads} threads, then {steps_1t} steps on 1 thread"}
 
 
 def copy_calibration(nbytes, iters):
@@ -337,8 +350,7 @@ def main():
         out["roofline"]["copy_GBps"] = cp["GBps"]
         out["roofline"]["frac_of_copy"] = ach / cp["GBps"]
     if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(system, args.cpu_steps, threads)
+        out["cpu_baseline"] = cpu_baseline(system, args.cpu_steps, max(1, args.cpu_steps // 5))
     print(json.dumps(out), flush=True)
 
 

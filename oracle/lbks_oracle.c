@@ -23,9 +23,14 @@
  * potential carries one ghost layer on every side, [nz+2][ny+2][nx+2].
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the element-wise loops (n >= 1); results do not depend on it. */
+void orc_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 #define ORC_Q 19
 

@@ -85,6 +85,8 @@ def lib():
             "orc_stream": (None, [I, I, I, I, P, P, P]),
             "orc_equilibrium": (None, [I, i64, P, P, P]),
             "orc_apply_sw": (None, [I, I, I, P, P, P, P]),
+            "orc_set_threads": (None, [I]),
+            "orc_max_threads": (I, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -92,6 +94,15 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's element-wise loops (its results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def _p(a: np.ndarray):
