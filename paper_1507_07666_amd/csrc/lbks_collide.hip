@@ -71,27 +71,34 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
         // byte offset of the source node r - v_p; when it falls outside the box the
         // loads are discarded by `ok` (and read 0 if beyond the plane)
         const unsigned src = off - (unsigned)((vx + nx * (vy + ny * vz)) * (int)sizeof(T));
-        T fl[NO];
+        // every load of this direction is issued before its first store: the
+        // compiler cannot reorder buffer loads above buffer stores, and a wait
+        // for a load issued after a store also waits for the store
+        T fl[NO], hat[NO], star[NO];
 #pragma unroll
         for (int l = 0; l < NO; ++l)
             fl[l] = (l < n) ? bload<T, BUF_NT>(plane_rsrc(fs, ((long long)l * Q + p) * N, sizeof(T), plane), src)
                             : (T)0;
         const T vn = bload<T, 0>(plane_rsrc(d.V, 0, sizeof(T), plane), src);
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            hat[j] = (j < n) ? bload<T, 0>(plane_rsrc(d.psihat, (long long)j * N, sizeof(T), plane), src) : (T)0;
+            star[j] = (W && j < n) ? bload<T, 0>(plane_rsrc(d.psistar, (long long)j * N, sizeof(T), plane), src)
+                                   : (T)0;
+        }
         const T cp = om * (T)d.xi[p];
         const T dp = dt * (T)d.chi[p] * vn;
 #pragma unroll
         for (int j = 0; j < NO; ++j) {
             if (j < n) {
-                const T hat = bload<T, 0>(plane_rsrc(d.psihat, (long long)j * N, sizeof(T), plane), src);
                 T o;
                 if (W) {
-                    const T star = bload<T, 0>(plane_rsrc(d.psistar, (long long)j * N, sizeof(T), plane), src);
-                    o = a * (c[j][j] * fl[j]) + cp * star - dp * hat;
+                    o = a * (c[j][j] * fl[j]) + cp * star[j] - dp * hat[j];
                 } else {
                     T g = (T)0;
 #pragma unroll
                     for (int l = 0; l <= j; ++l) g += c[l][j] * fl[l];
-                    o = a * g + (cp - dp) * hat;
+                    o = a * g + (cp - dp) * hat[j];
                 }
                 o = ok ? o : (T)0;
                 // populations are read once per step: stream them past the caches
