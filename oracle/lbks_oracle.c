@@ -407,7 +407,8 @@ void orc_forces(int nx, int ny, int nz, double h, int nnuc, const double *Z, con
     }
 }
 
-enum { ORC_XC_NONE = 0, ORC_XC_X = 1, ORC_XC_X_LYPLOCAL = 2, ORC_XC_X_PZ81 = 3, ORC_XC_B88_LYP = 4 };
+enum { ORC_XC_NONE = 0, ORC_XC_X = 1, ORC_XC_X_LYPLOCAL = 2, ORC_XC_X_PZ81 = 3, ORC_XC_B88_LYP = 4,
+       ORC_XC_B88_LYP_POLARISED = 5 };
 
 /*
  * Local exchange-correlation per unit charge (eps) and potential (v = d(rho eps)/drho)
@@ -532,16 +533,46 @@ void orc_gga_point(double rho, double sigma, double floor, double *fx, double *f
 }
 
 /*
+ * The same functionals for a fully spin-polarised density (every electron in one
+ * spin channel: rho_up = rho, rho_down = 0, as for the hydrogen atom of Table 1).
+ * Becke's exchange is a sum over spin channels, here the one channel with spin
+ * density n = rho and gradient g = sqrt(sigma):
+ *   f_x = -C n^(4/3) - beta n^(4/3) x^2 / (1 + 6 beta x asinh x),  x = g / n^(4/3).
+ * Lee-Yang-Parr correlation in its spin-resolved form has every term either
+ * proportional to rho_up rho_down or cancelling when rho_down = 0, so f_c = 0.
+ */
+void orc_gga_point_polarised(double rho, double sigma, double floor, double *fx, double *fc, double *fx_r,
+                             double *fc_r, double *fx_s, double *fc_s)
+{
+    const double pi = 3.14159265358979323846;
+    *fx = *fc = *fx_r = *fc_r = *fx_s = *fc_s = 0.0;
+    if (!(rho >= floor) || rho <= 0.0) return;
+    const double beta = 0.0042, C = 0.75 * cbrt(6.0 / pi);
+    double n13 = cbrt(rho), n43 = rho * n13;
+    double x = sqrt(sigma) / n43;
+    double as = asinh(x);
+    double q = 1.0 + 6.0 * beta * x * as;
+    double H = x * x / q;
+    double Hpx = (2.0 * q - 6.0 * beta * x * (as + x / sqrt(1.0 + x * x))) / (q * q);   /* H'(x) / x */
+    *fx = -C * n43 - beta * n43 * H;
+    /* d/dn at fixed g: -(4/3) C n^(1/3) - (4/3) beta n^(1/3) (H - x H'), as for one channel above */
+    *fx_r = -(4.0 / 3.0) * C * n13 - (4.0 / 3.0) * beta * n13 * (H - x * x * Hpx);
+    /* d/d sigma = -beta n^(4/3) H'(x) x / (2 sigma) = -beta (H'/x) / (2 n^(4/3)) */
+    *fx_s = -beta * Hpx / (2.0 * n43);
+}
+
+/*
  * Gradient-corrected exchange-correlation on the grid.  sigma = |D rho|^2 with
  * central differences D_a rho = (rho(r + e_a) - rho(r - e_a)) / 2h and rho = 0
  * outside the box; the potential is the exact derivative of the discrete energy
  * h^3 sum_r f(rho_r, sigma_r) with respect to rho_s, divided by h^3:
  *   v = df/drho - sum_a D_a [2 (df/dsigma) D_a rho]   (same central differences).
  * ex, ec: energy per particle (f / rho, zero where rho = 0) so that E = h^3 <rho|e>;
- * vx, vc: the exchange and correlation parts of v.
+ * vx, vc: the exchange and correlation parts of v.  polarised: the fully
+ * spin-polarised functionals (orc_gga_point_polarised), else spin-unpolarised.
  */
-void orc_gga(int nx, int ny, int nz, double h, const double *rho, double floor, double *ex, double *ec,
-             double *vx, double *vc)
+void orc_gga(int nx, int ny, int nz, double h, const double *rho, double floor, int polarised, double *ex,
+             double *ec, double *vx, double *vc)
 {
     const i64 N = (i64)nx * ny * nz;
     double *gx = (double *)calloc((size_t)N * 6, sizeof(double));   /* 2 f_s D_a rho, exchange then correlation */
@@ -558,7 +589,10 @@ void orc_gga(int nx, int ny, int nz, double h, const double *rho, double floor, 
                 double D[3] = {(xp - xm) * ih2, (yp - ym) * ih2, (zp - zm) * ih2};
                 double sigma = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
                 double fx, fc, fxr, fcr, fxs, fcs;
-                orc_gga_point(rho[s], sigma, floor, &fx, &fc, &fxr, &fcr, &fxs, &fcs);
+                if (polarised)
+                    orc_gga_point_polarised(rho[s], sigma, floor, &fx, &fc, &fxr, &fcr, &fxs, &fcs);
+                else
+                    orc_gga_point(rho[s], sigma, floor, &fx, &fc, &fxr, &fcr, &fxs, &fcs);
                 ex[s] = rho[s] > 0.0 ? fx / rho[s] : 0.0;
                 ec[s] = rho[s] > 0.0 ? fc / rho[s] : 0.0;
                 vx[s] = fxr;

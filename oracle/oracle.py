@@ -31,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbks_oracle.so")
 SRC_PATH = os.path.join(_HERE, "lbks_oracle.c")
 
-XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81, XC_B88_LYP = 0, 1, 2, 3, 4
+XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81, XC_B88_LYP, XC_B88_LYP_POLARISED = 0, 1, 2, 3, 4, 5
 Q = 19
 
 _lib = None
@@ -80,7 +80,8 @@ def lib():
             "orc_forces": (None, [I, I, I, D, I, P, P, D, P, P]),
             "orc_xc": (None, [I, i64, P, D, P, P, P, P]),
             "orc_gga_point": (None, [D, D, D, P, P, P, P, P, P]),
-            "orc_gga": (None, [I, I, I, D, P, D, P, P, P, P]),
+            "orc_gga": (None, [I, I, I, D, P, D, I, P, P, P, P]),
+            "orc_gga_point_polarised": (None, [D, D, D, P, P, P, P, P, P]),
             "orc_collide": (None, [I, i64, D, D, P, P, P, P, P, P, P]),
             "orc_stream": (None, [I, I, I, I, P, P, P]),
             "orc_equilibrium": (None, [I, i64, P, P, P]),
@@ -141,22 +142,25 @@ def time_step(omega: float, D: float, h: float) -> float:
 
 def xc_fields(kind: int, rho: np.ndarray, floor: float = 1e-14, dims=None, h=None):
     """Per-node exchange and correlation energies per particle and potentials.
-    The gradient-corrected kind (XC_B88_LYP) needs the grid (dims, h)."""
+    The gradient-corrected kinds (XC_B88_LYP, XC_B88_LYP_POLARISED) need the grid (dims, h)."""
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     n = rho.size
     ex, ec, vx, vc = (np.zeros_like(rho) for _ in range(4))
-    if kind == XC_B88_LYP:
+    if kind in (XC_B88_LYP, XC_B88_LYP_POLARISED):
         nx, ny, nz = dims
-        lib().orc_gga(nx, ny, nz, h, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
+        lib().orc_gga(nx, ny, nz, h, _p(rho), floor, 1 if kind == XC_B88_LYP_POLARISED else 0,
+                      _p(ex), _p(ec), _p(vx), _p(vc))
     else:
         lib().orc_xc(kind, n, _p(rho), floor, _p(ex), _p(ec), _p(vx), _p(vc))
     return ex, ec, vx, vc
 
 
-def gga_point(rho: float, sigma: float, floor: float = 1e-14):
-    """(f_x, f_c, df_x/drho, df_c/drho, df_x/dsigma, df_c/dsigma) of B88 + LYP."""
+def gga_point(rho: float, sigma: float, floor: float = 1e-14, polarised: bool = False):
+    """(f_x, f_c, df_x/drho, df_c/drho, df_x/dsigma, df_c/dsigma) of B88 + LYP,
+    spin-unpolarised or fully spin-polarised."""
     out = [ctypes.c_double() for _ in range(6)]
-    lib().orc_gga_point(rho, sigma, floor, *[ctypes.byref(o) for o in out])
+    fn = lib().orc_gga_point_polarised if polarised else lib().orc_gga_point
+    fn(rho, sigma, floor, *[ctypes.byref(o) for o in out])
     return tuple(o.value for o in out)
 
 

@@ -15,7 +15,15 @@ Table 1), spin-unpolarised.
     t_W and the Laplacian, written out independently here;
   * the partial derivatives match finite differences of the energy densities;
   * on the grid, the potential is the exact derivative of the discrete energy
-    h^3 sum f(rho, |D rho|^2) (central differences D), by finite differences.
+    h^3 sum f(rho, |D rho|^2) (central differences D), by finite differences;
+  * fully spin-polarised densities (one electron, as for H in Table 1): Becke's
+    exchange of the exact hydrogen density is -0.310 hartree (the value Table 1
+    lists for H; Becke 1988 gives -0.3098) and its local part the textbook LSD
+    -0.268; Becke's exchange obeys the spin-scaling relation
+    f_pol(rho, sigma) = f_unpol(2 rho, 4 sigma) / 2; Lee-Yang-Parr correlation,
+    written out here in its spin-resolved form (Miehlich, Savin, Stoll, Preuss
+    1989), equals the oracle's closed-shell form at rho_up = rho_down and
+    vanishes for a one-spin density (Table 1: V_c(H) = 0).
 """
 import math
 
@@ -117,8 +125,10 @@ def test_partial_derivatives(oracle_mod):
             assert f[vs] == pytest.approx(ds, rel=1e-6, abs=1e-12), (which, rho, sigma)
 
 
-def test_grid_potential_is_the_derivative_of_the_discrete_energy(oracle_mod):
+@pytest.mark.parametrize("polarised", [False, True])
+def test_grid_potential_is_the_derivative_of_the_discrete_energy(oracle_mod, polarised):
     O = oracle_mod
+    kind = O.XC_B88_LYP_POLARISED if polarised else O.XC_B88_LYP
     from paper_1507_07666_amd.inputs import radius2
     dims, h = (14, 12, 10), 0.3
     r2 = radius2(dims, h).ravel()
@@ -126,10 +136,10 @@ def test_grid_potential_is_the_derivative_of_the_discrete_energy(oracle_mod):
     rho = 2.0 * np.exp(-1.3 * np.sqrt(r2 + 0.04)) * (1.0 + 0.2 * rng.random(r2.size))
 
     def energy(rr):
-        ex, ec, _, _ = O.xc_fields(O.XC_B88_LYP, rr, 1e-14, dims, h)
+        ex, ec, _, _ = O.xc_fields(kind, rr, 1e-14, dims, h)
         return h ** 3 * float(np.sum(rr * (ex + ec)))
 
-    _, _, vx, vc = O.xc_fields(O.XC_B88_LYP, rho, 1e-14, dims, h)
+    _, _, vx, vc = O.xc_fields(kind, rho, 1e-14, dims, h)
     for trial in range(4):
         delta = np.zeros_like(rho)
         idx = rng.choice(rho.size, 25, replace=False)
@@ -138,3 +148,73 @@ def test_grid_potential_is_the_derivative_of_the_discrete_energy(oracle_mod):
         fd = (energy(rho + eps * delta) - energy(rho - eps * delta)) / (2 * eps)
         an = h ** 3 * float(np.dot(vx + vc, delta))
         assert an == pytest.approx(fd, rel=1e-7, abs=1e-13), (trial, an, fd)
+
+
+def test_polarised_exchange_of_the_hydrogen_atom(oracle_mod):
+    """n = e^(-2r) / pi, |grad n| = 2 n, one spin channel."""
+    O = oracle_mod
+    r = np.linspace(1e-6, 30.0, 30001)
+    n = np.exp(-2.0 * r) / math.pi
+    w = 4.0 * math.pi * r * r
+    b88 = np.array([O.gga_point(x, (2.0 * x) ** 2, 0.0, polarised=True)[0] for x in n])
+    lsd = np.array([O.gga_point(x, 0.0, 0.0, polarised=True)[0] for x in n])
+    assert simpson(w * b88, x=r) == pytest.approx(-0.310, abs=5e-4)      # Table 1, H
+    assert simpson(w * lsd, x=r) == pytest.approx(-0.268, abs=5e-4)
+    assert all(O.gga_point(x, (2.0 * x) ** 2, 0.0, polarised=True)[1] == 0.0 for x in n[::1000])
+
+
+def test_polarised_exchange_spin_scaling(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        rho = 10 ** rng.uniform(-4, 1.5)
+        sigma = rho ** (8.0 / 3.0) * 10 ** rng.uniform(-3, 2)
+        p = O.gga_point(rho, sigma, polarised=True)
+        u = O.gga_point(2.0 * rho, 4.0 * sigma)
+        assert p[0] == pytest.approx(0.5 * u[0], rel=1e-13)
+        assert p[2] == pytest.approx(u[2], rel=1e-13)               # d/drho: (1/2) * 2
+        assert p[4] == pytest.approx(2.0 * u[4], rel=1e-13)         # d/dsigma: (1/2) * 4
+
+
+def lyp_spin_resolved(ra, rb, ga2, gb2, gab):
+    """Lee-Yang-Parr correlation energy density for spin densities ra, rb with
+    |grad ra|^2, |grad rb|^2 and grad ra . grad rb (Miehlich et al. 1989)."""
+    a, b, c, d = LYP["a"], LYP["b"], LYP["c"], LYP["d"]
+    rho = ra + rb
+    g2 = ga2 + gb2 + 2.0 * gab
+    u = rho ** (-1.0 / 3.0)
+    om = math.exp(-c * u) / (1.0 + d * u) * rho ** (-11.0 / 3.0)
+    dl = c * u + d * u / (1.0 + d * u)
+    bracket = (ra * rb * (2.0 ** (11.0 / 3.0) * CF * (ra ** (8.0 / 3.0) + rb ** (8.0 / 3.0))
+                          + (47.0 / 18.0 - 7.0 * dl / 18.0) * g2 - (2.5 - dl / 18.0) * (ga2 + gb2)
+                          - (dl - 11.0) / 9.0 * (ra / rho * ga2 + rb / rho * gb2))
+               - 2.0 / 3.0 * rho ** 2 * g2 + (2.0 / 3.0 * rho ** 2 - ra ** 2) * gb2
+               + (2.0 / 3.0 * rho ** 2 - rb ** 2) * ga2)
+    return -4.0 * a / (1.0 + d * u) * ra * rb / rho - a * b * om * bracket
+
+
+def test_lyp_spin_resolved_form(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(4)
+    for _ in range(30):
+        rho = 10 ** rng.uniform(-3, 1.5)
+        sigma = rho ** (8.0 / 3.0) * 10 ** rng.uniform(-3, 2)
+        closed = lyp_spin_resolved(rho / 2, rho / 2, sigma / 4, sigma / 4, sigma / 4)
+        assert O.gga_point(rho, sigma)[1] == pytest.approx(closed, rel=1e-12)
+        one = lyp_spin_resolved(rho, 0.0, sigma, 0.0, 0.0)
+        assert abs(one) <= 1e-14 * abs(closed)
+        assert O.gga_point(rho, sigma, polarised=True)[1] == 0.0
+
+
+def test_polarised_partial_derivatives(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(6)
+    for _ in range(30):
+        rho = 10 ** rng.uniform(-4, 1.5)
+        sigma = rho ** (8.0 / 3.0) * 10 ** rng.uniform(-3, 2)
+        f = O.gga_point(rho, sigma, polarised=True)
+        hr, hs = 1e-4 * rho, 1e-4 * sigma
+        dr = (O.gga_point(rho + hr, sigma, polarised=True)[0] - O.gga_point(rho - hr, sigma, polarised=True)[0]) / (2 * hr)
+        ds = (O.gga_point(rho, sigma + hs, polarised=True)[0] - O.gga_point(rho, sigma - hs, polarised=True)[0]) / (2 * hs)
+        assert f[2] == pytest.approx(dr, rel=1e-6, abs=1e-12)
+        assert f[4] == pytest.approx(ds, rel=1e-6, abs=1e-12)
