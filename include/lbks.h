@@ -59,12 +59,15 @@ extern "C" {
  * compares with: Becke 1988 exchange + Lee-Yang-Parr 1988 correlation
  * (spin-unpolarised; the gradient is taken by central differences and the
  * potential is the exact derivative of the discrete energy; 32 more bytes of
- * device memory per node). */
+ * device memory per node), or the same for a fully spin-polarised density
+ * (every electron in one spin channel, as for the hydrogen atom of Table 1:
+ * Becke exchange of that channel, no Lee-Yang-Parr correlation). */
 #define LBKS_XC_NONE 0
 #define LBKS_XC_X 1
 #define LBKS_XC_X_LYPLOCAL 2
 #define LBKS_XC_X_PZ81 3
 #define LBKS_XC_B88_LYP 4
+#define LBKS_XC_B88_LYP_POLARISED 5
 
 /* precision: everything in FP64, or populations, orbitals, density and
  * potential stored and streamed in FP32 while the overlap, Cholesky factor,
@@ -91,7 +94,8 @@ typedef struct lbks_params {
     int32_t N[3];            /* nodes per axis, each in [4, 1024]; N0 N1 N2 < 2^29 */
     double h;                /* node spacing (bohr) */
     int32_t n_orb;           /* orbitals, 1..LBKS_MAX_ORB */
-    int32_t n_elec;          /* electrons; occupations 2,2,...,n_elec-2(n_orb-1) */
+    int32_t n_elec;          /* electrons; occupations 2,2,...,n_elec-2(n_orb-1), or 1 each
+                                with LBKS_XC_B88_LYP_POLARISED (n_elec = n_orb) */
     double omega;            /* BGK relaxation frequency (default 1) */
     double D;                /* second moment of the equilibrium weights xi_p (default 1/3) */
     int32_t ortho;           /* LBKS_ORTHO_* */
@@ -147,7 +151,8 @@ int lbks_params_default(lbks_params *p);
  * equilibrium, f_jp = xi_p psi^0_j (lattice Boltzmann equilibrium).
  * Rejects (LBKS_E_INVAL) parameters outside the stable region: omega in
  * (0, 2), D in (0, 7/18] (the relaxation stencil keeps a non-negative symbol),
- * n_elec in [1, 2 n_orb], a nonzero reserved field, or the collapsed scheme at
+ * n_elec outside (2 (n_orb - 1), 2 n_orb] (or != n_orb for the fully
+ * spin-polarised functional), a nonzero reserved field, or the collapsed scheme at
  * omega != 1.  LBKS_E_NOMEM if the device memory cannot be allocated.
  * The context owns its device memory until lbks_destroy. */
 int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ctx **out);

@@ -126,8 +126,12 @@ def lattice(D: float = 1.0 / 3.0):
     return v, w, xi, chi
 
 
-def occupations(n_elec: int, n_orb: int) -> np.ndarray:
-    """Closed-shell reading: 2 electrons per orbital, the last takes the rest."""
+def occupations(n_elec: int, n_orb: int, polarised: bool = False) -> np.ndarray:
+    """Closed-shell reading: 2 electrons per orbital, the last takes the rest.  A
+    fully spin-polarised density has one electron in each orbital."""
+    if polarised:
+        assert n_elec == n_orb, "one spin: one electron per orbital"
+        return np.ones(n_orb)
     occ = np.full(n_orb, 2.0)
     occ[-1] = n_elec - 2.0 * (n_orb - 1)
     return occ
@@ -229,7 +233,7 @@ class Oracle:
         self.N = prm.n_sites
         self.v, self.w, self.xi, self.chi = lattice(prm.D)
         self.occ = (np.asarray(prm.occ, dtype=np.float64) if prm.occ is not None
-                    else occupations(prm.n_elec, prm.n_orb))
+                    else occupations(prm.n_elec, prm.n_orb, prm.xc == XC_B88_LYP_POLARISED))
         self.f = np.zeros((prm.n_orb, Q, self.N))
         self.fpost = np.zeros_like(self.f)
         self.vh = np.zeros((nz + 2, ny + 2, nx + 2))

@@ -155,7 +155,12 @@ int validate(const lbks_params *p, std::string &why)
     }
     if (!(p->h > 0.0) || !isfinite(p->h)) { why = "h must be positive"; return LBKS_E_INVAL; }
     if (p->n_orb < 1 || p->n_orb > LBKS_MAX_ORB) { why = "n_orb out of [1, 16]"; return LBKS_E_INVAL; }
-    if (p->n_elec < 1 || p->n_elec > 2 * p->n_orb || p->n_elec <= 2 * (p->n_orb - 1)) {
+    if (p->xc == LBKS_XC_B88_LYP_POLARISED) {
+        if (p->n_elec != p->n_orb) {
+            why = "a fully spin-polarised density holds one electron per orbital: n_elec must equal n_orb";
+            return LBKS_E_INVAL;
+        }
+    } else if (p->n_elec < 1 || p->n_elec > 2 * p->n_orb || p->n_elec <= 2 * (p->n_orb - 1)) {
         why = "n_elec must satisfy 2(n_orb-1) < n_elec <= 2 n_orb";
         return LBKS_E_INVAL;
     }
@@ -165,7 +170,7 @@ int validate(const lbks_params *p, std::string &why)
         return LBKS_E_INVAL;
     }
     if (p->ortho != LBKS_ORTHO_GS && p->ortho != LBKS_ORTHO_W) { why = "bad ortho"; return LBKS_E_INVAL; }
-    if (p->xc < LBKS_XC_NONE || p->xc > LBKS_XC_B88_LYP) { why = "bad xc"; return LBKS_E_INVAL; }
+    if (p->xc < LBKS_XC_NONE || p->xc > LBKS_XC_B88_LYP_POLARISED) { why = "bad xc"; return LBKS_E_INVAL; }
     if (p->poisson_sweeps < 0 || p->poisson_sweeps > 64) { why = "poisson_sweeps out of [0, 64]"; return LBKS_E_INVAL; }
     if (p->precision != LBKS_FP64 && p->precision != LBKS_FP32_BULK) { why = "bad precision"; return LBKS_E_INVAL; }
     if (!(p->softening >= 0.0)) { why = "softening must be >= 0"; return LBKS_E_INVAL; }
@@ -215,7 +220,7 @@ Layout plan_layout(const lbks_params *p)
     take(L.e_part, (size_t)padded_cols(2 * no + NEBASE) * ntile * 8);
     take(L.r_part, (size_t)padded_cols(2) * ntile * 8);
     take(L.f_part, (size_t)padded_cols(3 * NUCG) * ntile * 8);
-    take(L.gga, p->xc == LBKS_XC_B88_LYP ? 4 * N * 8 : 0);
+    take(L.gga, p->xc >= LBKS_XC_B88_LYP ? 4 * N * 8 : 0);
     {
         const int widest = std::max(std::max(no * (no + 1) / 2, NMOM), std::max(2 * no + NEBASE, 3 * NUCG));
         take(L.g_part, (size_t)padded_cols(widest) * RG * 8);
@@ -535,8 +540,12 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     h.rho_floor = p->rho_floor;
     h.e_nn = 0.0;
     for (int j = 0; j < MAXO; ++j) h.occ[j] = 0.0;
-    for (int j = 0; j < p->n_orb; ++j) h.occ[j] = 2.0;
-    h.occ[p->n_orb - 1] = (double)p->n_elec - 2.0 * (p->n_orb - 1);
+    if (p->xc == LBKS_XC_B88_LYP_POLARISED) {
+        for (int j = 0; j < p->n_orb; ++j) h.occ[j] = 1.0;   // one spin: one electron per orbital
+    } else {
+        for (int j = 0; j < p->n_orb; ++j) h.occ[j] = 2.0;
+        h.occ[p->n_orb - 1] = (double)p->n_elec - 2.0 * (p->n_orb - 1);
+    }
     lattice_constants(p->D, h.xi, h.chi);
     h.f0 = at(L.f0);
     h.f1 = at(L.f1);
@@ -567,7 +576,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.precision = p->precision == LBKS_FP32_BULK ? 1 : 0;
     pl.no = orbital_bucket(p->n_orb);
     pl.wmode = p->ortho == LBKS_ORTHO_W;
-    pl.gga = p->xc == LBKS_XC_B88_LYP;
+    pl.gga = p->xc >= LBKS_XC_B88_LYP;
     pl.ntile = h.ntile;
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;

@@ -348,13 +348,28 @@ __device__ void overlap_partial(const T (&acc)[NO], int n, double *out, int stri
 //   f1 = a b rho^(-5/3) e^(-c u) / (1 + d u) (3 + 7 delta) / 72,
 //   u = rho^(-1/3), delta = c u + d u / (1 + d u).
 // Returns fx, fc and the derivatives of fx + fc with respect to rho (fr) and
-// sigma (fs); all zero below the density floor.
-static __device__ void gga_eval(double rho, double sigma, double floor, double &fx, double &fc, double &fr,
-                                double &fs)
+// sigma (fs); all zero below the density floor.  polarised: every electron in one
+// spin channel (n = rho, |grad n|^2 = sigma, a single e_s), where the
+// Lee-Yang-Parr correlation vanishes.
+static __device__ void gga_eval(double rho, double sigma, double floor, bool polarised, double &fx, double &fc,
+                                double &fr, double &fs)
 {
     fx = fc = fr = fs = 0.0;
     if (!(rho >= floor) || !(rho > 0.0)) return;
     const double PI = 3.14159265358979323846;
+    if (polarised) {
+        const double beta = 0.0042, C = 0.75 * cbrt(6.0 / PI);
+        const double n13 = cbrt(rho), n43 = rho * n13;
+        const double x = sqrt(sigma) / n43;
+        const double as = asinh(x);
+        const double q = 1.0 + 6.0 * beta * x * as;
+        const double H = x * x / q;
+        const double Hx = (2.0 * q - 6.0 * beta * x * (as + x / sqrt(1.0 + x * x))) / (q * q);   // H'(x) / x
+        fx = -C * n43 - beta * n43 * H;
+        fr = -(4.0 / 3.0) * n13 * (C + beta * (H - x * x * Hx));
+        fs = -beta * Hx / (2.0 * n43);
+        return;
+    }
     // exchange
     const double beta = 0.0042, C = 0.75 * cbrt(6.0 / PI);
     const double n = 0.5 * rho, n13 = cbrt(n), n43 = n * n13;

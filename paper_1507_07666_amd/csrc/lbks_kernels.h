@@ -31,7 +31,8 @@ __host__ __device__ constexpr int bricks_of(int nx, int ny, int nz)
 __host__ __device__ constexpr bool brick_partials(int ntile, int nbrick) { return nbrick <= ntile; }
 constexpr int NUCG = 16;       // nuclei per force-kernel pass
 constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
-constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP
+constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP (kinds from here on are gradient-corrected)
+constexpr int XC_GGA_POLARISED = 5;   // LBKS_XC_B88_LYP_POLARISED
 
 constexpr int RG = 32;         // first-level workgroups per instance of the finalize kernels
 

@@ -424,7 +424,8 @@ __global__ __launch_bounds__(BS) void k_gga(const InstDesc *__restrict__ descs, 
     double D[3];
     grad_rho<T>(d, s, x, y, z, D);
     double fx, fc, fr, fs;
-    gga_eval((double)((const T *)d.rho)[s], D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor, fx, fc, fr, fs);
+    gga_eval((double)((const T *)d.rho)[s], D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor,
+             d.xc == XC_GGA_POLARISED, fx, fc, fr, fs);
     const size_t N = (size_t)d.nsite;
     d.gga[s] = fr;
     d.gga[N + s] = 2.0 * fs * D[0];
@@ -454,7 +455,7 @@ __device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, 
 {
     double V = d.vext[s];
     if (d.hartree) V += d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)];
-    if (d.xc == XC_GGA) {
+    if (d.xc >= XC_GGA) {
         V += gga_potential(d, s, x, y, z);
     } else if (d.xc) {
         double ex, ec, vx, vc;
@@ -590,11 +591,12 @@ __global__ __launch_bounds__(BS) void k_energy_terms(const InstDesc *__restrict_
         }
         const double rho = (double)((const T *)d.rho)[s];
         double ex, ec, vx_, vc_;
-        if (d.xc == XC_GGA) {
+        if (d.xc >= XC_GGA) {
             // energies per volume; divided back by rho so that rho * e below is f
             double D[3], fx, fc, fr, fs;
             grad_rho<T>(d, s, x, y, z, D);
-            gga_eval(rho, D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor, fx, fc, fr, fs);
+            gga_eval(rho, D[0] * D[0] + D[1] * D[1] + D[2] * D[2], d.rho_floor, d.xc == XC_GGA_POLARISED, fx, fc,
+                     fr, fs);
             ex = rho > 0.0 ? fx / rho : 0.0;
             ec = rho > 0.0 ? fc / rho : 0.0;
         } else {

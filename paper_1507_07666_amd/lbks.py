@@ -24,6 +24,7 @@ LBKS_OK, LBKS_NOT_CONVERGED = 0, 1
 LBKS_E_INVAL, LBKS_E_NOMEM, LBKS_E_HIP, LBKS_E_NUMERIC, LBKS_E_STATE = -1, -2, -3, -4, -5
 LBKS_ORTHO_GS, LBKS_ORTHO_W = 0, 1
 LBKS_XC_NONE, LBKS_XC_X, LBKS_XC_X_LYPLOCAL, LBKS_XC_X_PZ81, LBKS_XC_B88_LYP = 0, 1, 2, 3, 4
+LBKS_XC_B88_LYP_POLARISED = 5
 LBKS_FP64, LBKS_FP32_BULK = 0, 1
 LBKS_INIT_GAUSS_NOISE, LBKS_INIT_RANDOM_GAUSS, LBKS_INIT_USER = 0, 1, 2
 LBKS_SCHEME_POPULATIONS, LBKS_SCHEME_COLLAPSED = 0, 1

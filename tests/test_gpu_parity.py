@@ -96,27 +96,35 @@ def test_relaxation_variants_fp64(L, variant):
     s.close()
 
 
-def lda_relaxed_orbitals(system, steps=200):
+def lda_relaxed_orbitals(system, steps=200, **kw):
     """A smooth start for the gradient-corrected functional: the seeded orbitals
     relaxed with the local functional on the oracle."""
-    o = O.oracle_for(system)
+    o = O.oracle_for(system, **kw)
     for _ in range(steps):
         o.step()
     psi, _ = o.state()
     return psi.reshape((system.n_orb,) + tuple(reversed(system.dims)))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_gradient_corrected_xc_matches_oracle(L, prec):
-    """Becke 88 + LYP from an LDA-relaxed start: 40 steps, state and energies."""
-    system = I.ne_atom().scaled(18, h=0.3)
-    say("gradient-corrected xc, precision", prec)
-    psi0 = lda_relaxed_orbitals(system)
-    p = L.params_for(system, init=L.LBKS_INIT_USER, xc=L.LBKS_XC_B88_LYP, precision=prec)
+@pytest.mark.parametrize("case", ["ne_fp64", "ne_fp32", "h_polarised", "three_polarised"])
+def test_gradient_corrected_xc_matches_oracle(L, case):
+    """Becke 88 + LYP from an LDA-relaxed start: 40 steps, state and energies;
+    spin-unpolarised Ne, and fully spin-polarised one- and three-electron atoms
+    (one electron per orbital, no correlation)."""
+    prec = 1 if case == "ne_fp32" else 0
+    if case.startswith("ne"):
+        system, xc, okw = I.ne_atom().scaled(18, h=0.3), L.LBKS_XC_B88_LYP, {}
+    else:
+        n = 1 if case == "h_polarised" else 3
+        system = I.System(case, (18, 18, 18), 0.3, [float(n)], [(0.0, 0.0, 0.0)], n, n, 0.1, seed=3 + n)
+        xc, okw = L.LBKS_XC_B88_LYP_POLARISED, dict(occ=np.ones(n))
+    say("gradient-corrected xc", case)
+    psi0 = lda_relaxed_orbitals(system, **okw)
+    p = L.params_for(system, init=L.LBKS_INIT_USER, xc=xc, precision=prec)
     s = L.Solver(p)
     s.set_nuclei(system.Z, system.R)
     s.set_orbitals(psi0)
-    o = O.oracle_for(system, xc=O.XC_B88_LYP)
+    o = O.oracle_for(system, xc=xc)
     o.set_orbitals(psi0)
     s.relax(40)
     for _ in range(40):
@@ -131,6 +139,9 @@ def test_gradient_corrected_xc_matches_oracle(L, prec):
         e, eo = s.energy(), o.energies(converge_poisson=True)
         assert abs(e["e_x"] - eo.e_x) <= 1e-5 and abs(e["e_c"] - eo.e_c) <= 1e-5
         assert abs(e["e_total"] - eo.e_total) <= 1e-5
+    if xc == L.LBKS_XC_B88_LYP_POLARISED:
+        assert s.energy()["e_c"] == 0.0
+        assert abs(s.energy()["n_electrons"] - system.n_elec) <= 1e-9
     s.close()
 
 
@@ -285,6 +296,9 @@ def test_error_paths(L):
     assert ei.value.code == L.LBKS_E_INVAL
     with pytest.raises(L.LbksError) as ei:
         s.set_nuclei([-1.0], [[0.0, 0.0, 0.0]])
+    assert ei.value.code == L.LBKS_E_INVAL
+    with pytest.raises(L.LbksError) as ei:          # one spin: one electron per orbital
+        L.Solver(L.params_for(system, xc=L.LBKS_XC_B88_LYP_POLARISED))
     assert ei.value.code == L.LBKS_E_INVAL
     with pytest.raises(L.LbksError) as ei:          # one more than LBKS_MAX_NUC
         s.set_nuclei([0.1] * 65, [[0.01 * k, 0.0, 0.0] for k in range(65)])
