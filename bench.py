@@ -127,6 +127,12 @@ def h2o_batch_run(count, check_every, max_steps):
     b = lbks.Batch()
     members = [b.add_system(sy, precision=lbks.LBKS_FP32_BULK, deps_tol=FP32_RULE["deps_tol"],
                             stop_checks=FP32_RULE["stop_checks"]) for sy in systems]
+    # update-kernel variant per grid size: timed on the first member of each size,
+    # the others take the cached choice (outside the timed region)
+    variants = {}
+    for sy, m in zip(systems, members):
+        v, _ = m.autotune(reps=3)
+        variants.setdefault(f"{sy.dims[0]}^3", v)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, steps = b.relax(max_steps, dE_tol, check_every)
@@ -141,6 +147,7 @@ def h2o_batch_run(count, check_every, max_steps):
             "solves": count, "converged": sum(1 for x in st if x == lbks.LBKS_OK),
             "wall_s": wall, "h2o_solves_per_s": count / wall, "orbital_site_updates_per_s": upd / wall,
             "steps_min": min(steps), "steps_max": max(steps), "nodes_total": sum(sy.n_sites for sy in systems),
+            "update_variants": variants,
             "e_total_first4": e}
 
 
