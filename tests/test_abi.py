@@ -90,6 +90,16 @@ def test_parameter_validation_host_side(L):
     assert L.lbks_estimate_bytes(ctypes.byref(fp32)) < est
     coll = lbks.params(32, 0.3, 1, 2, scheme=lbks.LBKS_SCHEME_COLLAPSED)
     assert L.lbks_estimate_bytes(ctypes.byref(coll)) < est / 4
+    # exchange-correlation kinds: the gradient-corrected ones need 32 more bytes per node;
+    # the fully spin-polarised one holds one electron per orbital
+    gga = lbks.params(32, 0.3, 1, 2, xc=lbks.LBKS_XC_B88_LYP)
+    assert L.lbks_estimate_bytes(ctypes.byref(gga)) >= est + 32 * N
+    pol = lbks.params(32, 0.3, 3, 3, xc=lbks.LBKS_XC_B88_LYP_POLARISED)
+    assert L.lbks_estimate_bytes(ctypes.byref(pol)) > 0
+    for n_orb, n_elec, xc in ((1, 2, lbks.LBKS_XC_B88_LYP_POLARISED), (3, 5, lbks.LBKS_XC_B88_LYP_POLARISED),
+                              (1, 2, lbks.LBKS_XC_B88_LYP_POLARISED + 1), (1, 2, -1)):
+        q = lbks.params(32, 0.3, n_orb, n_elec, xc=xc)
+        assert L.lbks_estimate_bytes(ctypes.byref(q)) == 0, (n_orb, n_elec, xc)
 
 
 def test_create_rejects_invalid_params_before_touching_a_device(L):
@@ -99,3 +109,13 @@ def test_create_rejects_invalid_params_before_touching_a_device(L):
         lbks.lbks_create(p)
     assert ei.value.code == lbks.LBKS_E_INVAL
     assert "7/18" in str(ei.value)
+
+
+def test_bench_refuses_several_gpus():
+    """The bench runs on one GPU; asked for more it exits with a message."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=root)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
