@@ -34,7 +34,8 @@ constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
 constexpr int XC_GGA = 4;      // LBKS_XC_B88_LYP (kinds from here on are gradient-corrected)
 constexpr int XC_GGA_POLARISED = 5;   // LBKS_XC_B88_LYP_POLARISED
 
-constexpr int RG = 32;         // first-level workgroups per instance of the finalize kernels
+constexpr int RG = 16;         // first-level workgroups per instance of the finalize kernels (8: 9.9, 16: 9.4,
+                               // 32: 10.2, 64: 12.4 us for the overlap finalize at 96^3)
 
 // Columns of a partial array padded to a whole number of chunks.
 __host__ __device__ constexpr int padded_cols(int nq) { return (nq + RCH - 1) / RCH * RCH; }
