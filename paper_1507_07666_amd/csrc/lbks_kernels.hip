@@ -236,25 +236,47 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
         double ps[NO];
 #pragma unroll
         for (int l = 0; l < NO; ++l) ps[l] = (l < n) ? (double)psi[(size_t)l * N + s] : 0.0;
+        // up to five orbitals, the coefficients and occupations are read before the
+        // first store: the compiler cannot tell that the stores leave them alone, and
+        // would otherwise reload them after every store and wait for it (for 8 and 16
+        // orbitals the tables would not fit the registers)
+        constexpr int NC = NO <= 5 ? NO : 1;
+        double c[NC][NC], cs[NC][NC], occ[NC];
+        if constexpr (NO <= 5) {
+#pragma unroll
+            for (int j = 0; j < NO; ++j) {
+                occ[j] = (j < n) ? d.occ[j] : 0.0;
+#pragma unroll
+                for (int l = 0; l < NO; ++l) {
+                    c[l][j] = (l <= j && j < n) ? d.C[l * MAXO + j] : 0.0;
+                    cs[l][j] = (W && l <= j && j < n) ? d.C[MAXO * MAXO + l * MAXO + j] : 0.0;
+                }
+            }
+        }
+        auto C_ = [&](int l, int j) { if constexpr (NO <= 5) return c[l][j]; else return d.C[l * MAXO + j]; };
+        auto Cs_ = [&](int l, int j) {
+            if constexpr (NO <= 5) return cs[l][j]; else return d.C[MAXO * MAXO + l * MAXO + j];
+        };
+        auto occ_ = [&](int j) { if constexpr (NO <= 5) return occ[j]; else return d.occ[j]; };
         double rho = 0.0;
 #pragma unroll
         for (int j = 0; j < NO; ++j) {
             if (j < n) {
                 double hat = 0.0;
                 if (W) {
-                    hat = ps[j] * d.C[j * MAXO + j];
+                    hat = ps[j] * C_(j, j);
                     double st = 0.0;
 #pragma unroll
-                    for (int l = 0; l <= j; ++l) st += ps[l] * d.C[MAXO * MAXO + l * MAXO + j];
+                    for (int l = 0; l <= j; ++l) st += ps[l] * Cs_(l, j);
                     pst[(size_t)j * N + s] = (T)st;
                 } else {
 #pragma unroll
-                    for (int l = 0; l <= j; ++l) hat += ps[l] * d.C[l * MAXO + j];
+                    for (int l = 0; l <= j; ++l) hat += ps[l] * C_(l, j);
                 }
                 const T hs = (T)hat;
                 ph[(size_t)j * N + s] = hs;
                 const double hd = (double)hs;
-                rho += d.occ[j] * hd * hd;
+                rho += occ_(j) * hd * hd;
             }
         }
         const T rs = (T)rho;
@@ -449,12 +471,13 @@ __device__ __forceinline__ double gga_potential(const InstDesc &d, int s, int x,
 
 // ------------------------------------------------------------- potential
 
-// V = V_ext + V_H + v_x + v_c at node s = (x, y, z), summed in that order in FP64.
+// V = V_ext + V_H + v_x + v_c at node s = (x, y, z), summed in that order in FP64,
+// with the node's Hartree value vh given.
 template <typename T>
-__device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, int y, int z)
+__device__ __forceinline__ double potential_with(const InstDesc &d, int s, int x, int y, int z, double vh)
 {
     double V = d.vext[s];
-    if (d.hartree) V += d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)];
+    if (d.hartree) V += vh;
     if (d.xc >= XC_GGA) {
         V += gga_potential(d, s, x, y, z);
     } else if (d.xc) {
@@ -464,6 +487,13 @@ __device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, 
         V += vc;
     }
     return V;
+}
+
+template <typename T>
+__device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, int y, int z)
+{
+    const double vh = d.hartree ? d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)] : 0.0;
+    return potential_with<T>(d, s, x, y, z, vh);
 }
 
 // The KS potential at every node (stored in the bulk precision for the collide,
@@ -484,7 +514,9 @@ __global__ __launch_bounds__(BS) void k_potential(const InstDesc *__restrict__ d
 
 // Last half-sweep of a step fused with the potential: each thread owns one x-pair
 // (one red and one black node), relaxes the black node, and then writes V at both
-// nodes (the red one is final since the preceding red half-sweep).
+// nodes (the red one is final since the preceding red half-sweep).  Every load
+// comes before the first store (the new black value is passed on in a register),
+// so no load waits for a store.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_sor_black_potential(const InstDesc *__restrict__ descs,
                                                             const int2 *__restrict__ tiles)
@@ -498,22 +530,25 @@ __global__ __launch_bounds__(BS) void k_sor_black_potential(const InstDesc *__re
     const int xh = t % hx, yz = t / hx, y = yz % ny, z = yz / ny;
     const int xb = 2 * xh + ((y + z + 1) & 1);
     const int xr = 2 * xh + ((y + z) & 1);
+    const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
+    const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(xb + 1);
+    const int sb = (z * ny + y) * nx + xb, sr = (z * ny + y) * nx + xr;
+    double *vh = d.vh;
+    double vb = 0.0, Vb = 0.0, Vr = 0.0;
     if (xb < nx) {
-        const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
-        const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(xb + 1);
-        double *vh = d.vh;
         const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
         const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
         const double rho = (double)((const T *)d.rho)[((size_t)z * ny + y) * nx + xb];
         const double gs = (nb + four_pi_h2 * rho) / 6.0;
-        vh[idx] = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
-        const int sb = (z * ny + y) * nx + xb;
-        ((T *)d.V)[sb] = (T)potential_at<T>(d, sb, xb, y, z);
+        vb = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
+        Vb = potential_with<T>(d, sb, xb, y, z, vb);
     }
-    if (xr < nx) {
-        const int sr = (z * ny + y) * nx + xr;
-        ((T *)d.V)[sr] = (T)potential_at<T>(d, sr, xr, y, z);
+    if (xr < nx) Vr = potential_at<T>(d, sr, xr, y, z);   // red V_H is not written here
+    if (xb < nx) {
+        vh[idx] = vb;
+        ((T *)d.V)[sb] = (T)Vb;
     }
+    if (xr < nx) ((T *)d.V)[sr] = (T)Vr;
 }
 
 // V_ext(r) = -sum_I Z_I / sqrt(|r - R_I|^2 + a^2); ZR = [Z, x, y, z] per nucleus, then a^2.
