@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--scheme", default="populations", choices=["populations", "collapsed"])
     ap.add_argument("--omega", type=float, default=1.0, help="relaxation parameter (populations only)")
+    ap.add_argument("--ortho", default="gs", choices=["gs", "w"],
+                    help="Cholesky Gram-Schmidt, or the paper's orthogonalisation source")
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -291,7 +293,8 @@ def main():
     system = workload(args.workload)
     prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
     scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED
-    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega)
+    ortho = lbks.LBKS_ORTHO_GS if args.ortho == "gs" else lbks.LBKS_ORTHO_W
+    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega, ortho=ortho)
     s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
 
     if args.variant is not None:
@@ -300,7 +303,7 @@ def main():
         solver.relax(args.warmup)
     # the LDS-staged field update (collapsed scheme, Gram-Schmidt, at most five
     # orbitals) has a single form: nothing to tune
-    bricks = scheme == lbks.LBKS_SCHEME_COLLAPSED and system.n_orb <= 5
+    bricks = scheme == lbks.LBKS_SCHEME_COLLAPSED and system.n_orb <= 5 and ortho == lbks.LBKS_ORTHO_GS
     if bricks:
         variant, tune_ms = None, None
     elif args.no_autotune or args.variant is not None:
@@ -336,7 +339,8 @@ def main():
         "config": {"workload": f"{system.name} atom {system.dims[0]}^3 nodes, h={system.h} bohr, "
                                f"softening {system.softening}, {system.n_orb} orbitals, "
                                f"{args.precision} {args.scheme}, seed {system.seed}"
-                               + (f", omega {args.omega}" if args.omega != 1.0 else ""),
+                               + (f", omega {args.omega}" if args.omega != 1.0 else "")
+                               + (", orthogonalisation source W" if args.ortho == "w" else ""),
                    "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
                    "omega": args.omega,
                    "update_variant": variant, "autotune_ms": tune_ms,

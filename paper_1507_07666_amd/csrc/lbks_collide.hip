@@ -165,13 +165,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
 // staged in LDS: a workgroup owns a brick of BX x BY nodes in x, y and marches
 // over BZ planes in z, keeping three planes of psi_hat_j and V with a one-node
 // halo in a ring (the plane after next is fetched into registers while a plane
-// is computed), so each field value is read from memory about once instead of
-// once per neighbour.  The terms are added in the same order as in k_collapsed;
-// terms from outside the box are exact zeros there and skipped here, so the new
-// orbitals are the same.  The overlap partial of the brick (psi_j psi_k summed
-// over its nodes in FP64, the planes in order) goes to tile slot b when the
-// instance has no more bricks than node tiles (slots from the brick count on are
-// zeroed by the bricks in turn); otherwise k_overlap_psi writes the partials.
+// is computed), so each field value is fetched twice per brick (planes z0 - 1 to
+// z0 + 2 for two computed planes) instead of once per neighbour; the loads are
+// global, not flat, so several stay in flight.  The terms are added in the same
+// order as in k_collapsed; terms from outside the box are exact zeros there and
+// skipped here, so the new orbitals are the same.  The overlap partial of the
+// brick (psi_j psi_k summed over its nodes in FP64, the planes in order) goes to
+// tile slot b when the instance has no more bricks than node tiles (slots from
+// the brick count on are zeroed by the bricks in turn); otherwise k_overlap_psi
+// writes the partials.
 template <typename T, int NO>
 __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restrict__ descs,
                                                         const int2 *__restrict__ bricks)
@@ -188,9 +190,9 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     const int x = x0 + tx, y = y0 + ty;
     const size_t N = (size_t)d.nsite;
-    const T *__restrict__ ph = (const T *)d.psihat;
-    const T *__restrict__ Vp = (const T *)d.V;
-    T *psi = (T *)d.psi;
+    const auto *__restrict__ ph = gmem((const T *)d.psihat);
+    const auto *__restrict__ Vp = gmem((const T *)d.V);
+    auto *psi = gmem((T *)d.psi);
     // the weights by speed class (|v_p|^2 = 0, 1, 2: velocities 0, 1, 7), and dt chi
     // formed as the node kernel forms it
     T cxi[3], cdc[3];

@@ -146,10 +146,18 @@ __device__ __forceinline__ GroupRef resolve_group(const int *list)
 }
 
 // A global-memory view of a device pointer (loads become global_load, not flat).
+// A flat load may be served by LDS or by memory, so before using its value the
+// compiler waits for every outstanding load; global loads are counted in order,
+// and several stay in flight.
 template <typename T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T *gmem(const T *p)
 {
     return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
 }
 
 // acc[c] += col[c * ntile + t] for c < NC and t = t0 + tid, t0 + tid + BS, ... < t1;
