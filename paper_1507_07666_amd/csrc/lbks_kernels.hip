@@ -230,9 +230,9 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
     for (int q = 0; q < NMOM; ++q) m[q] = 0.0;
     if (s < d.nsite) {
         const size_t N = (size_t)d.nsite;
-        const T *psi = (const T *)d.psi;
-        T *ph = (T *)d.psihat;
-        T *pst = (T *)d.psistar;
+        const auto *psi = gmem((const T *)d.psi);
+        auto *ph = gmem((T *)d.psihat);
+        auto *pst = gmem((T *)d.psistar);
         double ps[NO];
 #pragma unroll
         for (int l = 0; l < NO; ++l) ps[l] = (l < n) ? (double)psi[(size_t)l * N + s] : 0.0;
@@ -371,10 +371,10 @@ __global__ __launch_bounds__(BS) void k_sor(const InstDesc *__restrict__ descs,
     if (x >= nx) return;
     const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
     const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(x + 1);
-    double *vh = d.vh;
+    auto *vh = gmem(d.vh);
     const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
     const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
-    const double rho = (double)((const T *)d.rho)[((size_t)z * ny + y) * nx + x];
+    const double rho = (double)gmem((const T *)d.rho)[((size_t)z * ny + y) * nx + x];
     const double gs = (nb + four_pi_h2 * rho) / 6.0;
     vh[idx] = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
 }
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(BS) void k_residual_finalize(const InstDesc *__rest
 template <typename T>
 __device__ __forceinline__ void grad_rho(const InstDesc &d, int s, int x, int y, int z, double (&D)[3])
 {
-    const T *r = (const T *)d.rho;
+    const auto *r = gmem((const T *)d.rho);
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int sy = nx, sz = nx * ny;
     const double ih2 = 1.0 / (2.0 * d.h);
@@ -461,12 +461,13 @@ __device__ __forceinline__ double gga_potential(const InstDesc &d, int s, int x,
     const size_t N = (size_t)d.nsite;
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int sy = nx, sz = nx * ny;
-    const double *gx = d.gga + N, *gy = d.gga + 2 * N, *gz = d.gga + 3 * N;
+    const auto *g = gmem((const double *)d.gga);
+    const auto *gx = g + N, *gy = g + 2 * N, *gz = g + 3 * N;
     const double ih2 = 1.0 / (2.0 * d.h);
     double div = ((x + 1 < nx ? gx[s + 1] : 0.0) - (x > 0 ? gx[s - 1] : 0.0)) * ih2;
     div += ((y + 1 < ny ? gy[s + sy] : 0.0) - (y > 0 ? gy[s - sy] : 0.0)) * ih2;
     div += ((z + 1 < nz ? gz[s + sz] : 0.0) - (z > 0 ? gz[s - sz] : 0.0)) * ih2;
-    return d.gga[s] - div;
+    return g[s] - div;
 }
 
 // ------------------------------------------------------------- potential
@@ -476,13 +477,13 @@ __device__ __forceinline__ double gga_potential(const InstDesc &d, int s, int x,
 template <typename T>
 __device__ __forceinline__ double potential_with(const InstDesc &d, int s, int x, int y, int z, double vh)
 {
-    double V = d.vext[s];
+    double V = gmem(d.vext)[s];
     if (d.hartree) V += vh;
     if (d.xc >= XC_GGA) {
         V += gga_potential(d, s, x, y, z);
     } else if (d.xc) {
         double ex, ec, vx, vc;
-        xc_eval(d.xc, (double)((const T *)d.rho)[s], d.rho_floor, ex, ec, vx, vc);
+        xc_eval(d.xc, (double)gmem((const T *)d.rho)[s], d.rho_floor, ex, ec, vx, vc);
         V += vx;
         V += vc;
     }
@@ -492,7 +493,7 @@ __device__ __forceinline__ double potential_with(const InstDesc &d, int s, int x
 template <typename T>
 __device__ __forceinline__ double potential_at(const InstDesc &d, int s, int x, int y, int z)
 {
-    const double vh = d.hartree ? d.vh[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)] : 0.0;
+    const double vh = d.hartree ? gmem(d.vh)[((size_t)(z + 1) * (d.ny + 2) + (y + 1)) * (d.nx + 2) + (x + 1)] : 0.0;
     return potential_with<T>(d, s, x, y, z, vh);
 }
 
@@ -533,22 +534,23 @@ __global__ __launch_bounds__(BS) void k_sor_black_potential(const InstDesc *__re
     const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
     const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(xb + 1);
     const int sb = (z * ny + y) * nx + xb, sr = (z * ny + y) * nx + xr;
-    double *vh = d.vh;
+    auto *vh = gmem(d.vh);
     double vb = 0.0, Vb = 0.0, Vr = 0.0;
     if (xb < nx) {
         const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
         const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
-        const double rho = (double)((const T *)d.rho)[((size_t)z * ny + y) * nx + xb];
+        const double rho = (double)gmem((const T *)d.rho)[((size_t)z * ny + y) * nx + xb];
         const double gs = (nb + four_pi_h2 * rho) / 6.0;
         vb = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
         Vb = potential_with<T>(d, sb, xb, y, z, vb);
     }
     if (xr < nx) Vr = potential_at<T>(d, sr, xr, y, z);   // red V_H is not written here
+    auto *Vo = gmem((T *)d.V);
     if (xb < nx) {
         vh[idx] = vb;
-        ((T *)d.V)[sb] = (T)Vb;
+        Vo[sb] = (T)Vb;
     }
-    if (xr < nx) ((T *)d.V)[sr] = (T)Vr;
+    if (xr < nx) Vo[sr] = (T)Vr;
 }
 
 // V_ext(r) = -sum_I Z_I / sqrt(|r - R_I|^2 + a^2); ZR = [Z, x, y, z] per nucleus, then a^2.
