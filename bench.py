@@ -36,13 +36,15 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def k1_bytes_per_launch(n_orb, nsite, s, scheme):
+def k1_bytes_per_launch(n_orb, nsite, s, scheme, wmode=False):
     """Algorithmic HBM bytes of one stream-collide launch: per orbital-site 2 Q s
     (populations in and out) + s (psi_hat stencil centre, read once) + s (psi out);
-    per site s (potential).  The collapsed scheme moves only 2 s per orbital-site + s."""
+    per site s (potential).  The collapsed scheme moves only 2 s per orbital-site + s.
+    With the orthogonalisation source W, psi* is read too: s more per orbital-site."""
+    w = n_orb * s if wmode else 0
     if scheme == 0:
-        return nsite * (n_orb * (2 * 19 * s + 2 * s) + s)
-    return nsite * (n_orb * 2 * s + s)
+        return nsite * (n_orb * (2 * 19 * s + 2 * s) + s + w)
+    return nsite * (n_orb * 2 * s + s + w)
 
 
 def measured_traffic(key):
@@ -349,7 +351,7 @@ def main():
     }
     if k1_n:
         avg_s = k1_ms / k1_n * 1e-3
-        alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme)
+        alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme, ortho == lbks.LBKS_ORTHO_W)
         ach = alg / avg_s / 1e9
         tkey = f"{args.workload}_{args.precision}_" + (f"v{variant}" if scheme == 0 else "collapsed" if bricks else "")
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
