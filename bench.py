@@ -8,7 +8,11 @@ run every `--check-every` steps inside the timed region.
 Default workload: Ne atom, 96^3 nodes at 0.2 bohr, softening 0.05, 5 orbitals,
 FP64, seeded random Gaussian-enveloped start (seed 2).  Metric: orbital-site
 updates per second (orbitals x nodes x steps / wall time), inputs resident in
-HBM.  Prints one JSON line.
+HBM.  The same JSON line also carries the other parts of the metric: the
+64-molecule H2O batch (solves/s until every member meets the FP32 rule, with the
+energy error of the members that have a stored oracle reference), one rate of
+the seeded serving stream (p50/p99 latency, solves/s), and CH4 128^3 time to
+|E - E_oracle| < 1e-5 Ha in FP64 and in FP32 on the GPU.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -116,6 +120,49 @@ def copy_calibration(nbytes, iters):
             "GBps": 2 * nbytes / (ms * 1e-3) / 1e9, "frac_of_8TBps": 2 * nbytes / (ms * 1e-3) / 8e12}
 
 
+def golden_energy(name):
+    """Converged total energy of a stored FP64 oracle reference (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    return json.load(open(path))["energies"]["e_total"]
+
+
+def fp32_gain_run(max_steps=6000, chunk=100, tol=1e-5):
+    """CH4 128^3 (the precision workload) from its seeded start, in FP64 and in FP32
+    bulk on the GPU, each relaxed in chunks of `chunk` steps until its total energy
+    (Hartree potential converged, lbks_energy) is within `tol` of the converged FP64
+    oracle reference.  Wall time includes the energy evaluations."""
+    import torch
+    from paper_1507_07666_amd import inputs as I
+    from paper_1507_07666_amd import lbks
+    ref = golden_energy("ch4")
+    if ref is None:
+        return None
+    sy = I.ch4()
+    out = {"workload": f"CH4 128^3 at 0.2 bohr, 5 orbitals, seed {sy.seed}; time until |E - E_oracle| < {tol:g} Ha, "
+                       f"energy checked every {chunk} steps", "e_oracle": ref, "tol_Ha": tol}
+    for name, prec in (("fp64", lbks.LBKS_FP64), ("fp32", lbks.LBKS_FP32_BULK)):
+        s = lbks.Solver.for_system(sy, precision=prec)
+        v, _ = s.autotune(reps=3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, e = 0, None
+        while steps < max_steps:
+            s.relax(chunk)
+            steps += chunk
+            e = s.energy()["e_total"]
+            if abs(e - ref) < tol:
+                break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s.close()
+        out[name] = {"wall_s": wall, "steps": steps, "dE_Ha": e - ref, "reached": abs(e - ref) < tol,
+                     "update_variant": v}
+    out["gain"] = out["fp64"]["wall_s"] / out["fp32"]["wall_s"]
+    return out
+
+
 def h2o_batch_run(count, check_every, max_steps):
     """64 H2O molecules (uneven grids) in one batch, FP32 bulk, until every one meets
     the FP32 stopping rule (energy within 2e-6 Ha and eigenvalue sum within 1e-6 Ha
@@ -141,6 +188,12 @@ def h2o_batch_run(count, check_every, max_steps):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     upd = sum(sy.n_orb * sy.n_sites * k for sy, k in zip(systems, steps))
+    # members with a stored FP64 oracle reference: their energy error
+    dE = {}
+    for i, m in enumerate(members):
+        ref = golden_energy(f"h2o_{i}")
+        if ref is not None:
+            dE[i] = m.energy()["e_total"] - ref
     e = [m.energy()["e_total"] for m in members[:4]]
     b.close()
     return {"workload": f"{count} H2O, grids {{64,80,96,112}}^3 at 0.2 bohr, 5 orbitals, FP32 bulk, "
@@ -150,7 +203,9 @@ def h2o_batch_run(count, check_every, max_steps):
             "wall_s": wall, "h2o_solves_per_s": count / wall, "orbital_site_updates_per_s": upd / wall,
             "steps_min": min(steps), "steps_max": max(steps), "nodes_total": sum(sy.n_sites for sy in systems),
             "update_variants": variants,
-            "e_total_first4": e}
+            "e_total_first4": e,
+            "dE_vs_oracle_Ha": {str(k): v for k, v in dE.items()},
+            "max_abs_dE_vs_oracle_Ha": max((abs(v) for v in dE.values()), default=None)}
 
 
 def bo_md_run(n_steps, n=80, softening=0.2):
@@ -206,6 +261,9 @@ def bo_md_run(n_steps, n=80, softening=0.2):
 
 
 def serve_run(n_requests, rate, check_every, budget_gb, grids):
+    """The seeded serving stream (seed 50) at `rate` Poisson arrivals per second,
+    continuous batching under an HBM budget; p50/p99 latency from arrival to the
+    last point's result, and solves (points) per second over the whole run."""
     from paper_1507_07666_amd import inputs as I
     from paper_1507_07666_amd import serve
     reqs = I.serving_stream(n_requests, rate=rate, seed=50, grids=grids)
@@ -217,7 +275,10 @@ def serve_run(n_requests, rate, check_every, budget_gb, grids):
     srv.close()
     out = serve.summarize(res, wall)
     out.update({"rate_per_s": rate, "budget_gb": budget_gb, "peak_slots": srv.peak_active,
-                "peak_bytes": srv.peak_used, "grids": list(grids)})
+                "peak_bytes": srv.peak_used, "grids": list(grids),
+                "workload": f"serving stream, seed 50, {n_requests} requests at {rate:g}/s (half atoms Z 1..10, "
+                            f"half 8-point scans of CH4/NH3/H2O), grids {list(grids)}, h 0.2, FP32 bulk, FP32 rule",
+                "all_converged": all(p.status == 0 for r in res for p in r.points)})
     return out
 
 
@@ -259,8 +320,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default update-kernel variant")
     ap.add_argument("--variant", type=int, default=None, help="fix the update-kernel variant (no autotuning)")
     ap.add_argument("--batch-count", type=int, default=64)
-    ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--rate", type=float, default=2.0, help="serving arrivals per second")
+    ap.add_argument("--requests", type=int, default=12)
+    ap.add_argument("--rate", type=float, default=0.5, help="serving arrivals per second")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the orbital-site update rate (no H2O batch, serving or FP32-gain legs)")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--mode", default="solve", choices=["solve", "copy"],
                     help="copy: time the library's plain copy kernel (bandwidth calibration)")
@@ -364,6 +427,14 @@ def main():
         out["roofline"]["frac_of_copy"] = ach / cp["GBps"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(system, args.cpu_steps, max(1, args.cpu_steps // 5))
+    if not args.no_extras and args.workload == "ne96":
+        # the other two parts of the metric, and the FP32-vs-FP64 time to the same accuracy
+        print("[bench] 64 H2O batch", file=sys.stderr, flush=True)
+        out["h2o_batch"] = h2o_batch_run(args.batch_count, 100, 20000)
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serve_run(args.requests, args.rate, 100, args.budget_gb, I_SERVE_GRIDS)
+        print("[bench] FP32 gain", file=sys.stderr, flush=True)
+        out["fp32_gain"] = fp32_gain_run()
     print(json.dumps(out), flush=True)
 
 

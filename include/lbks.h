@@ -184,12 +184,36 @@ int lbks_set_nuclei(lbks_ctx *ctx, int32_t n, const double *Z, const double *xyz
 int lbks_relax(lbks_ctx *ctx, int64_t max_steps, double dE_tol, int32_t check_every,
                int64_t *steps_done);
 
-/* Energies of the current state (host struct).  First relaxes the Hartree
- * potential for the current density to a relative residual <= 1e-12, or to
- * the roundoff floor of a fine grid (the residual <= 1e-9 and no more than 10 %
- * below its value 50 sweeps earlier); this state change is kept.  Then
- * evaluates every term of the total energy. */
+/* Energies of the current state (host struct `out`, owned by the caller), the
+ * quantities of the Kohn-Sham functional (section "Kohn-Sham formulation": the
+ * kinetic, external, Hartree and exchange-correlation terms of the KS
+ * Hamiltonian and the density) and the eigenvalues of the KS equation (eq. KSE)
+ * that the results section reports for atoms (Table 1, Fig. 1).  The orbitals
+ * are those of the current populations, orthonormalised; eps_j is the Rayleigh
+ * quotient <psi_hat_j|K_h psi_hat_j> + <psi_hat_j|S_chi(V psi_hat_j)> of the
+ * lattice operator whose steady state the relaxation reaches, with
+ * K_h u = -(S_xi u - u)/(D h^2); e_total = sum_j occ_j <psi_hat_j|K_h psi_hat_j>
+ * + <V_ext|rho> + 1/2 <V_H|rho> + <rho|eps_x + eps_c> + E_NN.  First relaxes the
+ * Hartree potential for the current density to a relative residual <= 1e-12,
+ * or to the roundoff floor of a fine grid (the residual <= 1e-9 and no more than
+ * 10 % below its value 50 sweeps earlier); this state change is kept.
+ * LBKS_E_INVAL if out is NULL, LBKS_E_STATE without nuclei or potential,
+ * LBKS_E_NUMERIC if the overlap is not positive definite or the Hartree
+ * relaxation does not converge. */
 int lbks_energy(lbks_ctx *ctx, lbks_energies *out);
+
+/* The relaxation operator projected on the current orthonormalised orbitals
+ * (host, FP64, row-major n_orb x n_orb, n_H >= n_orb^2, owned by the caller):
+ *   H_jk = <psi_hat_j | K_h psi_hat_k + S_chi(V psi_hat_k)>,
+ * with V built from their density as in lbks_energy (same Hartree relaxation,
+ * kept).  Its diagonal holds the eps_j of lbks_energy; its eigenvalues are the
+ * Ritz values of the operator on the span of the orbitals.  The KS equation
+ * (eq. KSE) determines the occupied levels, not the orbitals inside a set of
+ * nearly equal levels, which the relaxation (eq. KSLB-2) separates only
+ * slowly; the Ritz values do not depend on such rotations.  LBKS_E_INVAL if H
+ * is NULL or too small, LBKS_E_STATE without nuclei or potential,
+ * LBKS_E_NUMERIC if the overlap or an entry is not finite. */
+int lbks_hamiltonian(lbks_ctx *ctx, double *H, size_t n_H);
 
 /* Forces on the nuclei (host, FP64, F[3 I + c] for nucleus I and axis c, in
  * hartree per bohr, n_F >= 3 * nuclei) for the current state, as used by
@@ -207,9 +231,14 @@ int lbks_forces(lbks_ctx *ctx, double *F, size_t n_F);
 
 /* Copy the current orthonormal orbitals (host, FP64, [n_orb][z][y][x],
  * n_psi >= n_orb * sites) and optionally the density (host, n_rho >= sites;
- * rho may be NULL).  <psi_hat_j|psi_hat_k> = delta_jk; each orbital's sign is
- * arbitrary and degenerate orbitals may mix.  LBKS_E_INVAL if a buffer is too
- * small. */
+ * rho may be NULL), the solution of the KS equations with their orthogonality
+ * constraints (section "Kohn-Sham formulation": the orbitals phi_j, eq. ORTOG,
+ * and the density rho = sum_j occ_j |phi_j|^2).  The orbitals are the moments
+ * psi_j = sum_p f_jp of the current populations (kinetic representation,
+ * section "The kinetic approach to Kohn-Sham theory") after Gram-Schmidt:
+ * <psi_hat_j|psi_hat_k> = delta_jk; each orbital's sign is arbitrary and
+ * degenerate orbitals may mix.  The caller owns both buffers.  LBKS_E_INVAL if
+ * psi is NULL or a buffer is too small; the state is not changed. */
 int lbks_orbitals(lbks_ctx *ctx, double *psi, size_t n_psi, double *rho, size_t n_rho);
 
 /* Release the context and all its device memory. */
@@ -249,24 +278,31 @@ size_t lbks_estimate_bytes(const lbks_params *p);
 int lbks_set_timing(lbks_ctx *ctx, int32_t enable);
 int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
-/* Update-kernel variants 0..7: bit 0 computes the per-workgroup overlap partial
+/* Update-kernel variants 0..15: bit 0 computes the per-workgroup overlap partial
  * S = Phi^T Phi on the matrix cores (V_MFMA_F64_16X16X4F64) instead of a wave
  * butterfly, bit 1 compiles the kernel for 8 waves per SIMD, bit 2 runs the
  * workgroups in dispatch order instead of giving each XCD one contiguous range
- * of tiles.  Every variant computes the same arithmetic; only the overlap's
- * summation order differs with bit 0 (bit 2 changes nothing in the results).
- * The LDS-staged omega = 1 update (Gram-Schmidt, at most five orbitals) has one
- * form and ignores the variant.  Defaults: 4 for FP64, 3 for FP32.
- * lbks_set_variant: LBKS_E_INVAL outside 0..7. */
+ * of tiles, bit 3 gives each lane of the population update 16 bytes of
+ * x-consecutive nodes (2 in FP64, 4 in FP32) read and written with one access
+ * per plane (orbital buckets of at most five; bits 0 and 1 are then unused, and
+ * larger buckets ignore bit 3).  Every variant computes the same per-node
+ * arithmetic; the overlap's summation order differs with bits 0 and 3, and the
+ * compiler may contract a product into a fused multiply-add differently in the
+ * wide form (last-bit differences); bit 2 changes nothing in the results.  The
+ * LDS-staged omega = 1 update (Gram-Schmidt, at most five orbitals) has one form
+ * and ignores the variant; the collapsed node-per-lane update ignores bit 3.
+ * Defaults: 4 for FP64, 3 for FP32.  lbks_set_variant: LBKS_E_INVAL outside
+ * 0..15. */
 int lbks_set_variant(lbks_ctx *ctx, int32_t variant);
 int lbks_get_variant(const lbks_ctx *ctx);
 
-/* Time every update-kernel variant `reps` times on the context's current state
- * and keep the fastest (state unchanged).  Choices are cached per (precision,
- * orbital bucket, orthogonalisation, scheme, node count) for the process; with
- * force = 0 a cached choice is reused without timing.  chosen (may be NULL)
- * receives the variant, avg_ms (NULL, or 8 doubles) the per-launch times
- * (-1 when the cache answered).  LBKS_E_STATE if no potential is set. */
+/* Time every distinct update-kernel variant `reps` times on the context's
+ * current state and keep the fastest (state unchanged).  Choices are cached per
+ * (precision, orbital bucket, orthogonalisation, scheme, node count) for the
+ * process; with force = 0 a cached choice is reused without timing.  chosen
+ * (may be NULL) receives the variant, avg_ms (NULL, or 16 doubles) the
+ * per-launch times, -1 for a variant not timed (the same kernel as a lower one)
+ * and for all when the cache answered.  LBKS_E_STATE if no potential is set. */
 int lbks_autotune(lbks_ctx *ctx, int32_t reps, int32_t force, int32_t *chosen, double *avg_ms);
 
 /* Plain device-to-device copy of `bytes` (a multiple of 16) on `stream` with
@@ -297,6 +333,7 @@ int lbks_batch_detach(lbks_batch *b, lbks_ctx *ctx);
  * attach order.  Returns the number of contexts attached. */
 int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
                      int32_t *status, int64_t *steps);
+
 int lbks_batch_size(const lbks_batch *b);
 
 /* The hipStream_t the batch launches on (members must be created on it). */

@@ -243,6 +243,7 @@ class Oracle:
         self.e_prev = None          # stopping rule: (energy, sum of eps) of the previous check, kept across relax calls
         self.passes = 0             # consecutive passing checks
         self.omega_sor = self.L.orc_sor_omega(nx, ny, nz)
+        self.fields = None          # orbital fields psi_j of the omega = 1 field step (step_fields), else None
 
     # -- inputs
     def set_nuclei(self, Z, R):
@@ -265,10 +266,13 @@ class Oracle:
     def set_orbitals(self, psi0):
         psi0 = np.ascontiguousarray(psi0, dtype=np.float64).reshape(self.prm.n_orb, self.N)
         self.e_prev = None
+        self.fields = None
         self.L.orc_equilibrium(self.prm.n_orb, self.N, _p(self.xi), _p(psi0), _p(self.f))
 
     # -- pieces of one step
     def moment(self):
+        if self.fields is not None:
+            return self.fields.copy()
         psi = np.empty((self.prm.n_orb, self.N))
         self.L.orc_moment(self.prm.n_orb, self.N, _p(self.f), _p(psi))
         return psi
@@ -342,6 +346,11 @@ class Oracle:
         if self.vext is None:
             raise RuntimeError("no potential set")
         p = self.prm
+        if self.fields is not None:
+            # leave the field form: the populations at equilibrium with the fields
+            # (at omega = 1 the step below does not read them beyond their moment)
+            self.L.orc_equilibrium(p.n_orb, self.N, _p(self.xi), _p(self.fields), _p(self.f))
+            self.fields = None
         psi = self.moment()
         psihat, psistar, g, _ = self.orthonormalise(psi)
         rho = self.density(psihat)
@@ -353,6 +362,36 @@ class Oracle:
                            _p(psistar), _p(psihat), _p(V), _p(self.fpost))
         nx, ny, nz = p.dims
         self.L.orc_stream(p.n_orb, nx, ny, nz, _p(self.v), _p(self.fpost), _p(self.f))
+        self.steps += 1
+
+    def step_fields(self):
+        """One step at omega = 1 on the orbital fields alone.  With omega = 1 the
+        relaxed part (1 - omega) g of the collision vanishes, so the new moment of
+        the lattice Boltzmann equation depends only on the orthonormalised fields:
+        summing the streamed post-collision populations over p gives
+            psi_j <- S_xi psi*_j - dt S_chi(V psi_hat_j),  (S_w u)(r) = sum_p w_p u(r - v_p),
+        zero outside the box (psi* = psi_hat: Gram-Schmidt mode).  Same steps 1-6 as step();
+        the populations are not formed.  Used to reach the fixed point with less work."""
+        if self.vext is None:
+            raise RuntimeError("no potential set")
+        p = self.prm
+        if p.omega != 1.0:
+            raise ValueError("the field step holds at omega = 1 only")
+        if p.ortho != "gs":
+            raise ValueError("the field step is written for Gram-Schmidt orthonormalisation")
+        psi = self.moment()
+        psihat, psistar, _, _ = self.orthonormalise(psi, with_g=False)
+        rho = self.density(psihat)
+        if p.hartree:
+            self.hartree_boundary(rho)
+            self.sor(rho, p.poisson_sweeps)
+        V, _ = self.potential(rho)
+        new = np.empty_like(psi)
+        for j in range(p.n_orb):
+            a = apply_sw(p.dims, self.v, self.xi, psistar[j])
+            b = apply_sw(p.dims, self.v, self.chi, V * psihat[j])
+            new[j] = a - p.dt * b
+        self.fields = new
         self.steps += 1
 
     # -- results
@@ -414,6 +453,36 @@ class Oracle:
         et = e_kin + e_ext + e_h + e_x + e_c + self.e_nn
         return Energies(et, e_kin, e_ext, e_h, e_x, e_c, self.e_nn, ne, res, eps, self.steps)
 
+    def hamiltonian(self, converge_poisson=True, tol=1e-12):
+        """The relaxation operator projected on the current orthonormalised orbitals,
+        H_jk = <psi_hat_j | K_h psi_hat_k + S_chi(V psi_hat_k)>, with V built from
+        their density exactly as in energies().  Its diagonal is eps_j (the
+        Rayleigh quotients of the eigenvalue reading); its eigenvalues are the Ritz
+        values of the operator (I - M)/dt on the orbitals' span, which do not
+        depend on how the orbitals are rotated inside that span.  Returns
+        (H, ritz) with ritz the eigenvalues' real parts in ascending order."""
+        p = self.prm
+        h3 = p.h ** 3
+        psihat, _, _, _ = self.orthonormalise(self.moment(), with_g=False)
+        rho = self.density(psihat)
+        if p.hartree:
+            if converge_poisson:
+                self.e_prev = None
+                self.converge_poisson(rho, tol)
+        V, _ = self.potential(rho)
+        n = p.n_orb
+        W = np.empty((n, self.N))
+        for k in range(n):
+            u = np.ascontiguousarray(psihat[k])
+            su = apply_sw(p.dims, self.v, self.xi, u)
+            W[k] = -(su - u) / (p.D * p.h * p.h) + apply_sw(p.dims, self.v, self.chi, V * u)
+        H = np.empty((n, n))
+        for j in range(n):
+            for k in range(n):
+                H[j, k] = h3 * self.L.orc_dot(self.N, _p(np.ascontiguousarray(psihat[j])), _p(W[k]))
+        ritz = np.sort(np.linalg.eigvals(H).real)
+        return H, ritz
+
     def forces(self) -> np.ndarray:
         """Hellmann-Feynman forces on the nuclei, [n][3] hartree/bohr, from the
         density of the orthonormalised current orbitals (Born-Oppenheimer scenario
@@ -429,7 +498,7 @@ class Oracle:
         self.L.orc_forces(nx, ny, nz, p.h, len(Z), _p(Z), _p(R), p.softening, _p(rho), _p(F))
         return F
 
-    def relax(self, max_steps, dE_tol=0.0, check_every=100, progress=None):
+    def relax(self, max_steps, dE_tol=0.0, check_every=100, progress=None, fields=False):
         """Run steps in chunks of check_every.  After each chunk (only if dE_tol > 0)
         the energies with the current Hartree potential are compared with the
         previous chunk's: the check passes if the total energy moved by less than
@@ -439,14 +508,16 @@ class Oracle:
         across calls until the state is changed by new nuclei, potential or
         orbitals, or a Poisson-converged energy evaluation.  Returns
         (0 converged | 1 step limit, steps done).  `progress(steps, energy)` is
-        called after each check."""
+        called after each check.  fields=True takes the omega = 1 field step
+        (step_fields), which reaches the same fixed point."""
         done = 0
+        advance = self.step_fields if fields else self.step
         check_every = max(1, int(check_every))
         need = max(1, int(self.prm.stop_checks))
         while done < max_steps:
             n = min(check_every, max_steps - done)
             for _ in range(n):
-                self.step()
+                advance()
             done += n
             if dE_tol > 0:
                 en = self.energies(converge_poisson=False)
@@ -474,3 +545,139 @@ def oracle_for(system, **kw) -> Oracle:
     o.set_nuclei(system.Z, system.R)
     o.set_orbitals(system.psi0())
     return o
+
+
+class ConcurrentDynamics:
+    """Electrons and nuclei moved together (the concurrent scenario of the section
+    on concurrent dynamics, eq. KSLBCD), in this reading:
+
+      * the orbitals are complex and the populations are at equilibrium with them,
+        f_jp = xi_p psi_j (the omega = 1 reading of the relaxation, where the
+        populations carry nothing beyond their moment), so the two-step
+        time-centred lattice equation advances the moments:
+            psi_j^{n+1} = psi_j^{n-1} - 2 i h H psi_j^n,
+            H u = K_h u + S_chi(V u),  K_h u = -(S_xi u - u) / (D dx^2),
+        H being the operator whose steady state the relaxation reaches (its
+        Rayleigh quotients are the eps_j), with the potential and orthogonality
+        sources turned by i as printed;
+      * U_jp = kappa w_p q_p E_j phi_j has no zeroth or first moment, so with the
+        populations at equilibrium it leaves the orbitals unchanged: kappa = 0,
+        and the energy is kept by the time-centred scheme itself;
+      * W = 0: the evolution is unitary up to the scheme's own error, which keeps
+        the orbitals orthonormal (the drift is measured, not corrected);
+      * start: psi^0 = the orthonormalised current orbitals (a relaxed ground
+        state), V_H converged for their density, and
+        psi^1 = psi^0 - i h H psi^0 - (h^2/2) H H psi^0;
+      * each step first rebuilds V from rho^n = sum_j occ_j |psi_j^n|^2 (multipole
+        boundary and K_P warm-started red/black sweeps, as in the relaxation),
+        then takes the step above;
+      * the nuclei (moved by the caller) enter through V_ext; forces are the
+        Hellmann-Feynman forces of the instantaneous density.
+    h is the time step in atomic units of real time.  Test infrastructure only."""
+
+    def __init__(self, o: "Oracle", h: float):
+        self.o = o
+        self.h = float(h)
+        p = o.prm
+        if p.omega != 1.0 or p.ortho != "gs":
+            raise ValueError("concurrent dynamics starts from the omega = 1 Gram-Schmidt relaxation")
+        psihat, _ = o.state()
+        self.prev = psihat.astype(np.complex128)
+        rho = self.density(self.prev)
+        if p.hartree:
+            o.converge_poisson(rho)
+        V, _ = o.potential(rho)
+        h1 = self.apply_h(self.prev, V)
+        h2 = self.apply_h(h1, V)
+        self.cur = self.prev - 1j * self.h * h1 - 0.5 * self.h * self.h * h2
+        self.steps = 0
+
+    # -- pieces
+    def density(self, psi):
+        re = np.ascontiguousarray(psi.real)
+        im = np.ascontiguousarray(psi.imag)
+        return self.o.density(re) + self.o.density(im)
+
+    def apply_h(self, psi, V):
+        """H psi for complex psi [n][N], on the real and imaginary parts."""
+        p = self.o.prm
+        out = np.empty_like(psi)
+        for j in range(psi.shape[0]):
+            parts = []
+            for u in (np.ascontiguousarray(psi[j].real), np.ascontiguousarray(psi[j].imag)):
+                su = apply_sw(p.dims, self.o.v, self.o.xi, u)
+                parts.append(-(su - u) / (p.D * p.h * p.h) + apply_sw(p.dims, self.o.v, self.o.chi, V * u))
+            out[j] = parts[0] + 1j * parts[1]
+        return out
+
+    def potential_now(self):
+        """V of the current density after the step's Hartree sweeps."""
+        p = self.o.prm
+        rho = self.density(self.cur)
+        if p.hartree:
+            self.o.hartree_boundary(rho)
+            self.o.sor(rho, p.poisson_sweeps)
+        V, _ = self.o.potential(rho)
+        return V
+
+    def step(self):
+        V = self.potential_now()
+        new = self.prev - 2j * self.h * self.apply_h(self.cur, V)
+        self.prev, self.cur = self.cur, new
+        self.steps += 1
+
+    # -- results
+    def staggered_overlap(self):
+        """h^3 <psi_j^{n-1}|psi_j^n> per orbital (complex): its real part is exactly
+        conserved by the time-centred step when H is symmetric."""
+        h3 = self.o.prm.h ** 3
+        return np.array([h3 * np.vdot(self.prev[j], self.cur[j]) for j in range(self.cur.shape[0])])
+
+    def overlap(self):
+        """h^3 <psi_j^n|psi_k^n> (complex Hermitian matrix)."""
+        h3 = self.o.prm.h ** 3
+        return h3 * (self.cur.conj() @ self.cur.T)
+
+    def energies(self, converge_poisson=True, tol=1e-12) -> Energies:
+        """Kohn-Sham energies of psi^n (as Oracle.energies, with Re<psi|.|psi>)."""
+        o, p = self.o, self.o.prm
+        h3 = p.h ** 3
+        rho = self.density(self.cur)
+        res = 0.0
+        if p.hartree:
+            if converge_poisson:
+                res, _ = o.converge_poisson(rho, tol)
+            else:
+                res = o.poisson_residual(rho)
+        V, (ex, ec, vx, vc) = o.potential(rho)
+        eps = np.empty(p.n_orb)
+        e_kin = 0.0
+        for j in range(p.n_orb):
+            kin = pot = 0.0
+            for u in (np.ascontiguousarray(self.cur[j].real), np.ascontiguousarray(self.cur[j].imag)):
+                su = apply_sw(p.dims, o.v, o.xi, u)
+                ku = np.ascontiguousarray(-(su - u) / (p.D * p.h * p.h))
+                vu = apply_sw(p.dims, o.v, o.chi, V * u)
+                kin += h3 * o.L.orc_dot(o.N, _p(u), _p(ku))
+                pot += h3 * o.L.orc_dot(o.N, _p(u), _p(vu))
+            eps[j] = kin + pot
+            e_kin += o.occ[j] * kin
+        rho = np.ascontiguousarray(rho)
+        e_ext = h3 * o.L.orc_dot(o.N, _p(o.vext), _p(rho))
+        vhi = o.vh_interior()
+        e_h = 0.5 * h3 * o.L.orc_dot(o.N, _p(vhi), _p(rho)) if p.hartree else 0.0
+        e_x = h3 * o.L.orc_dot(o.N, _p(rho), _p(ex)) if p.xc != XC_NONE else 0.0
+        e_c = h3 * o.L.orc_dot(o.N, _p(rho), _p(ec)) if p.xc != XC_NONE else 0.0
+        ne = h3 * o.L.orc_sum(o.N, _p(rho))
+        et = e_kin + e_ext + e_h + e_x + e_c + o.e_nn
+        return Energies(et, e_kin, e_ext, e_h, e_x, e_c, o.e_nn, ne, res, eps, self.steps)
+
+    def forces(self) -> np.ndarray:
+        """Hellmann-Feynman forces of the current density on the nuclei, [n][3]."""
+        o, p = self.o, self.o.prm
+        rho = np.ascontiguousarray(self.density(self.cur))
+        Z, R = o.nuclei
+        F = np.zeros((len(Z), 3))
+        nx, ny, nz = p.dims
+        o.L.orc_forces(nx, ny, nz, p.h, len(Z), _p(Z), _p(R), p.softening, _p(rho), _p(F))
+        return F

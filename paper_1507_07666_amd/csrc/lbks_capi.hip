@@ -86,6 +86,8 @@ struct lbks_batch {
     size_t mem_bytes = 0;
     double *d_gather = nullptr;         // [members][GATHER_W]
     const double **d_scal = nullptr;    // members' scalar blocks
+    uint64_t member_epoch = 0;          // bumped by every attach and detach
+    uint64_t table_epoch = ~0ull;       // member_epoch the device tables were built for
     bool dirty = true;
     int bparity = 0;                    // population buffer parity within the current plan
     int64_t epoch_steps = 0;            // steps since the plan was built
@@ -759,10 +761,12 @@ extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t
     return LBKS_NOT_CONVERGED;
 }
 
-extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
+namespace {
+
+// Orthonormalise the current orbitals and, with Hartree on, converge V_H for
+// their density (the state lbks_energy and lbks_hamiltonian evaluate).
+int converge_hartree(lbks_ctx *c)
 {
-    if (!c || !out) return LBKS_E_INVAL;
-    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     int rc;
     reset_rule(c);   // the Hartree relaxation below changes the state
     if ((rc = enqueue_orthonormalise(c))) return rc;
@@ -791,11 +795,51 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
             if ((rc = enqueue_sweeps(c, 10))) return rc;
         }
     }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
+{
+    if (!c || !out) return LBKS_E_INVAL;
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    int rc;
+    if ((rc = converge_hartree(c))) return rc;
     if ((rc = enqueue_energy(c))) return rc;
     double errf = 0.0;
     if ((rc = read_energies(c, out, &errf))) return rc;
     if (errf != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
     if (!c->p.hartree) out->poisson_residual = 0.0;
+    return 0;
+}
+
+extern "C" int lbks_hamiltonian(lbks_ctx *c, double *H, size_t n_H)
+{
+    if (!c || !H) return LBKS_E_INVAL;
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    const size_t n = (size_t)c->p.n_orb;
+    if (n_H < n * n) return fail(c, LBKS_E_INVAL, "H buffer too small");
+    if (n * n > (n + 1) * (size_t)c->h.nsite) return fail(c, LBKS_E_INVAL, "grid too small to stage H");
+    int rc;
+    if ((rc = converge_hartree(c))) return rc;
+    if (c->plan.gga) KCHK(c, launch_gga(c->plan, c->stream));
+    KCHK(c, launch_potential(c->plan, 1, c->stream));
+    for (int j0 = 0; j0 < (int)n;) {
+        int rows = 0;
+        KCHK(c, launch_ham_rows(c->plan, j0, &rows, c->stream));
+        j0 += rows;
+    }
+    std::vector<double> buf(n * n + 1);
+    HIPCHK(c, hipMemcpyAsync(buf.data(), c->h.stage, n * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(buf.data() + n * n, c->h.scal + SC_ERR, sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (buf[n * n] != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+    for (size_t q = 0; q < n * n; ++q) {
+        if (!isfinite(buf[q])) return fail(c, LBKS_E_NUMERIC, "projected operator not finite");
+        H[q] = buf[q];
+    }
     return 0;
 }
 
@@ -928,6 +972,8 @@ extern "C" int lbks_autotune(lbks_ctx *c, int32_t reps, int32_t force, int32_t *
     double ms_v[N_VARIANTS];
     int rc = 0;
     for (int v = 0; v < N_VARIANTS && !rc; ++v) {
+        ms_v[v] = -1.0;
+        if (!variant_distinct(v, c->plan.no, pops)) continue;   // same kernel as a variant already timed
         c->plan.variant = v;
         // one untimed launch, then `reps` timed ones; each launch recomputes the same
         // output from the same inputs
@@ -1069,20 +1115,22 @@ int batch_build(lbks_batch *b)
         return o;
     };
     struct Off {
-        size_t desc, site, ghost, sor, inst, brick;
-        int n_site, n_ghost, n_sor, n_brick;
+        size_t desc, site, ghost, sor, inst, brick, site_w;
+        int n_site, n_ghost, n_sor, n_brick, n_site_w;
     };
     std::vector<Off> go(b->groups.size());
     for (size_t k = 0; k < b->groups.size(); ++k) {
         const BatchGroup &g = b->groups[k];
         Off &o = go[k];
-        o.n_site = o.n_ghost = o.n_sor = o.n_brick = 0;
+        o.n_site = o.n_ghost = o.n_sor = o.n_brick = o.n_site_w = 0;
+        const int kw = wide_nodes(g.precision ? 4 : 8);
         for (int i : g.members) {
             const InstDesc &h = b->members[i]->h;
             o.n_site += h.ntile;
             o.n_ghost += h.ntile_ghost;
             o.n_sor += h.ntile_sor;
             o.n_brick += h.ntile_brick;
+            o.n_site_w += (h.ntile + kw - 1) / kw;
         }
         o.desc = take(sizeof(InstDesc) * g.members.size());
         o.site = take(sizeof(int2) * o.n_site);
@@ -1090,6 +1138,7 @@ int batch_build(lbks_batch *b)
         o.sor = take(sizeof(int2) * o.n_sor);
         o.inst = take(sizeof(int) * g.members.size());
         o.brick = take(sizeof(int2) * o.n_brick);
+        o.site_w = take(sizeof(int2) * o.n_site_w);
     }
     const size_t gather_off = take(sizeof(double) * GATHER_W * std::max(m, 1));
     const size_t scal_off = take(sizeof(double *) * std::max(m, 1));
@@ -1113,7 +1162,9 @@ int batch_build(lbks_batch *b)
         int2 *tr = (int2 *)(host.data() + o.sor);
         int *ti = (int *)(host.data() + o.inst);
         int2 *tb = (int2 *)(host.data() + o.brick);
-        int ns = 0, ng = 0, nr = 0, nb = 0;
+        int2 *tw = (int2 *)(host.data() + o.site_w);
+        const int kw = wide_nodes(g.precision ? 4 : 8);
+        int ns = 0, ng = 0, nr = 0, nb = 0, nw = 0;
         bool all_brick = true;
         for (size_t q = 0; q < g.members.size(); ++q) {
             const lbks_ctx *c = b->members[g.members[q]];
@@ -1124,6 +1175,7 @@ int batch_build(lbks_batch *b)
             for (int t = 0; t < d.ntile_ghost; ++t) tg[ng++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_sor; ++t) tr[nr++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_brick; ++t) tb[nb++] = make_int2((int)q, t);
+            for (int t = 0; t < (d.ntile + kw - 1) / kw; ++t) tw[nw++] = make_int2((int)q, t);
             all_brick = all_brick && brick_partials(d.ntile, d.ntile_brick);
             ti[q] = (int)q;
         }
@@ -1140,6 +1192,8 @@ int batch_build(lbks_batch *b)
         pl.tt.n_inst = (int)g.members.size();
         pl.tt.brick = (const int2 *)(base + o.brick);
         pl.tt.n_brick = o.n_brick;
+        pl.tt.site_w = (const int2 *)(base + o.site_w);
+        pl.tt.n_site_w = o.n_site_w;
         pl.brick_partials = all_brick;
         pl.precision = g.precision;
         pl.no = g.no;
@@ -1152,6 +1206,7 @@ int batch_build(lbks_batch *b)
     for (int i = 0; i < m; ++i) hs[i] = b->members[i]->h.scal;
     b->d_gather = (double *)(base + gather_off);
     b->d_scal = (const double **)(base + scal_off);
+    b->table_epoch = b->member_epoch;
     if (hipMemcpyAsync(b->mem, host.data(), off, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return batch_fail(b, LBKS_E_HIP, "batch table upload failed");
@@ -1213,6 +1268,7 @@ extern "C" int lbks_batch_attach(lbks_batch *b, lbks_ctx *c)
     b->members.push_back(c);
     b->running.assign(b->members.size(), 1);
     c->batch = b;
+    b->member_epoch += 1;
     b->dirty = true;
     return 0;
 }
@@ -1226,6 +1282,7 @@ extern "C" int lbks_batch_detach(lbks_batch *b, lbks_ctx *c)
     b->running.assign(b->members.size(), 1);
     b->groups.clear();
     c->batch = nullptr;
+    b->member_epoch += 1;
     b->dirty = true;
     return 0;
 }
@@ -1249,7 +1306,14 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
     b->dirty = true;
     if (check_every < 1) check_every = 1;
     std::vector<double> gat((size_t)GATHER_W * std::max(m, 1));
+    // The gather reads the members' scalar blocks through the pointer table of the
+    // last build; a relax that stepped nothing (max_steps == 0, no member with a
+    // potential) or follows an attach or detach builds the table first.
     auto gather = [&]() -> int {
+        if (!b->d_scal || b->table_epoch != b->member_epoch) {
+            const int e = batch_build(b);
+            if (e) return e;
+        }
         if (launch_gather(b->d_scal, m, GATHER_W, b->d_gather, b->stream)) return LBKS_E_HIP;
         if (hipMemcpyAsync(gat.data(), b->d_gather, sizeof(double) * GATHER_W * m, hipMemcpyDeviceToHost,
                            b->stream) != hipSuccess ||

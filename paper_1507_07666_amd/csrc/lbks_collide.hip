@@ -113,6 +113,142 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
     overlap_partial_v<T, NO, V>(acc, n, d.s_part + tr.tile, d.ntile);
 }
 
+// The same update with K = 16 / sizeof(T) x-consecutive nodes per lane (2 in FP64, 4
+// in FP32): for a run of consecutive flat nodes the pull sources along v_p are the
+// same run shifted by the uniform flat offset d_p = v_px + nx (v_py + ny v_pz), so one
+// 16-byte access per plane serves the lane (at any element offset; planes are read
+// through guarded resources).  Workgroup w covers K node tiles; its overlap partial
+// goes to tile slot K w and the other K - 1 slots are zeroed.  The arithmetic per
+// node is that of k_stream_collide.  Variant bit 2 (dispatch order) applies; the
+// overlap partial is always the wave-halving form.
+template <typename T, int NO, bool W>
+__global__ __launch_bounds__(BS) void k_stream_collide_wide(const InstDesc *__restrict__ descs,
+                                                            const int2 *__restrict__ tiles, int parity, int linear)
+{
+    constexpr int K = 16 / (int)sizeof(T);
+    const TileRef tr = resolve(tiles, linear);
+    const InstDesc &d = descs[tr.inst];
+    const int n = orbitals<NO>(d);
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const long long N = d.nsite;
+    const unsigned plane = (unsigned)N * (unsigned)sizeof(T);
+    const int s0 = (tr.tile * BS + (int)threadIdx.x) * K;
+    const bool whole = s0 + K <= d.nsite;           // all K nodes inside the grid
+    const void *fs = parity ? d.f1 : d.f0;
+    void *fd = parity ? d.f0 : d.f1;
+    const T a = (T)(1.0 - d.omega);
+    const T om = (T)d.omega;
+    const T dt = (T)d.dt;
+    T c[NO][NO];
+#pragma unroll
+    for (int l = 0; l < NO; ++l)
+#pragma unroll
+        for (int j = 0; j < NO; ++j) c[l][j] = (T)d.C[l * MAXO + j];
+    int xs[K], ys[K], zs[K];
+    bool valid[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int s = s0 + i;
+        valid[i] = s < d.nsite;
+        xs[i] = s % nx;
+        const int yz = s / nx;
+        ys[i] = yz % ny;
+        zs[i] = yz / ny;
+    }
+    const unsigned off = (unsigned)s0 * (unsigned)sizeof(T);
+    T acc[NO][K];
+#pragma unroll
+    for (int j = 0; j < NO; ++j)
+#pragma unroll
+        for (int i = 0; i < K; ++i) acc[j][i] = (T)0;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const int vx = VX(p), vy = VY(p), vz = VZ(p);
+        bool ok[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            ok[i] = valid[i] && (unsigned)(xs[i] - vx) < (unsigned)nx && (unsigned)(ys[i] - vy) < (unsigned)ny &&
+                    (unsigned)(zs[i] - vz) < (unsigned)nz;
+        // guarded byte offset of the source run r - v_p (modulo 2^32: a run wholly
+        // before the plane wraps far out of range and reads zeros, discarded by ok)
+        const unsigned src = off + PLANE_GUARD - (unsigned)((vx + nx * (vy + ny * vz)) * (int)sizeof(T));
+        T fl[NO][K], hat[NO][K], star[NO][K], vn[K];
+#pragma unroll
+        for (int l = 0; l < NO; ++l) {
+            if (l < n) bload16<T, K, BUF_NT>(fl[l], plane_rsrc_guarded(fs, ((long long)l * Q + p) * N, sizeof(T), plane), src);
+            else
+#pragma unroll
+                for (int i = 0; i < K; ++i) fl[l][i] = (T)0;
+        }
+        bload16<T, K, 0>(vn, plane_rsrc_guarded(d.V, 0, sizeof(T), plane), src);
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            if (j < n) bload16<T, K, 0>(hat[j], plane_rsrc_guarded(d.psihat, (long long)j * N, sizeof(T), plane), src);
+            if (W && j < n) bload16<T, K, 0>(star[j], plane_rsrc_guarded(d.psistar, (long long)j * N, sizeof(T), plane), src);
+        }
+        const T cp = om * (T)d.xi[p];
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            if (j < n) {
+                T o[K];
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    const T dp = dt * (T)d.chi[p] * vn[i];
+                    T v;
+                    if (W) {
+                        v = a * (c[j][j] * fl[j][i]) + cp * star[j][i] - dp * hat[j][i];
+                    } else {
+                        T g = (T)0;
+#pragma unroll
+                        for (int l = 0; l <= j; ++l) g += c[l][j] * fl[l][i];
+                        v = a * g + (cp - dp) * hat[j][i];
+                    }
+                    o[i] = ok[i] ? v : (T)0;
+                    acc[j][i] += o[i];
+                }
+                const auto rd = plane_rsrc(fd, ((long long)j * Q + p) * N, sizeof(T), plane);
+                if (whole) {
+                    bstore16<T, K, BUF_NT>(o, rd, off);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < K; ++i)
+                        if (valid[i]) bstore<T, BUF_NT>(o[i], rd, off + (unsigned)(i * (int)sizeof(T)));
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+        if (j < n) {
+            const auto rp = plane_rsrc(d.psi, (long long)j * N, sizeof(T), plane);
+            if (whole) {
+                bstore16<T, K, 0>(acc[j], rp, off);
+            } else {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    if (valid[i]) bstore<T, 0>(acc[j][i], rp, off + (unsigned)(i * (int)sizeof(T)));
+            }
+        }
+    }
+    double prod[NO * (NO + 1) / 2];
+    {
+        int q = 0;
+#pragma unroll
+        for (int j = 0; j < NO; ++j)
+#pragma unroll
+            for (int k = 0; k <= j; ++k) {
+                double sum = 0.0;
+#pragma unroll
+                for (int i = 0; i < K; ++i) sum += (double)acc[j][i] * (double)acc[k][i];
+                prod[q++] = sum;
+            }
+    }
+    const int slot = tr.tile * K;
+    block_sum_store(prod, npair_of(n), d.s_part + slot, d.ntile);
+    if ((int)threadIdx.x < npair_of(n))
+        for (int t = slot + 1; t < slot + K && t < d.ntile; ++t) d.s_part[(size_t)threadIdx.x * d.ntile + t] = 0.0;
+}
+
 // omega = 1 without populations: psi_j(r) <- sum_p [xi_p psi*_j - dt chi_p V psi_hat_j](r - v_p),
 // exactly the moment of the population update at omega = 1.
 template <typename T, int NO, bool W, int V>
@@ -303,8 +439,29 @@ static int launch_collapsed_v(const Plan &pl, hipStream_t st)
     });
 }
 
+// Wide form (variant bit 3) for buckets of at most five orbitals; larger buckets
+// take the node-per-lane kernel of the other bits.
+static int launch_stream_collide_wide(const Plan &pl, int parity, hipStream_t st)
+{
+    return dispatch_tnw(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        if constexpr (TG::NO <= 5) {
+            constexpr int K = 16 / (int)sizeof(typename TG::T);
+            const int grid = pl.tt.site_w ? pl.tt.n_site_w : (pl.ntile + K - 1) / K;
+            k_stream_collide_wide<typename TG::T, TG::NO, TG::W><<<grid, BS, 0, st>>>(pl.d_desc, pl.tt.site_w, parity,
+                                                                                     (pl.variant >> 2) & 1);
+            return (int)hipGetLastError();
+        } else {
+            return (int)hipErrorInvalidValue;
+        }
+    });
+}
+
+bool stream_collide_is_wide(const Plan &pl) { return (pl.variant & 8) && pl.no <= 5; }
+
 int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
 {
+    if (stream_collide_is_wide(pl)) return launch_stream_collide_wide(pl, parity, st);
     switch (pl.variant & 3) {
     case 0: return launch_stream_collide_v<0>(pl, parity, st);
     case 1: return launch_stream_collide_v<1>(pl, parity, st);

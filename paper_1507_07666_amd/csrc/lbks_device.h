@@ -304,6 +304,37 @@ __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned o
             __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r, (int)off, 0, AUX);
 }
 
+// 16 bytes per lane: K = 16 / sizeof(T) x-consecutive nodes in one buffer access.
+template <typename T, int K, int AUX>
+__device__ __forceinline__ void bload16(T (&out)[K], __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    static_assert(K * sizeof(T) == 16, "16 bytes per lane");
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
+    __builtin_memcpy(out, &v, 16);
+}
+template <typename T, int K, int AUX>
+__device__ __forceinline__ void bstore16(const T (&in)[K], __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    static_assert(K * sizeof(T) == 16, "16 bytes per lane");
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) v;
+    __builtin_memcpy(&v, in, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, AUX);
+}
+
+// A plane resource widened by PLANE_GUARD bytes on each side, for 16-byte loads
+// at any element offset: a vector with at least one element inside the plane
+// is then wholly in range (a hardware range check may drop a partly-outside
+// access).  The guard bytes lie inside the context's one allocation (the planes
+// that are read this way are neither its first nor its last buffer).
+constexpr unsigned PLANE_GUARD = 256;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_guarded(const void *base, long long elems, int elem_bytes,
+                                                                     unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((char *)base + elems * elem_bytes - PLANE_GUARD, 0,
+                                             (int)(bytes + 2 * PLANE_GUARD), BUF_WORD3);
+}
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Overlap partial of one workgroup, S_jk = sum over its nodes of psi_j psi_k

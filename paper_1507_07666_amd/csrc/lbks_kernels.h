@@ -93,6 +93,7 @@ struct TileTables {
     const int2 *sor = nullptr;    int n_sor = 0;
     const int *inst = nullptr;    int n_inst = 0;   // instance list for per-instance kernels
     const int2 *brick = nullptr;  int n_brick = 0;
+    const int2 *site_w = nullptr; int n_site_w = 0;   // tiles of the wide update: BS * (16 / element size) nodes
 };
 
 // Launch plan of one kernel family: descriptor array on the device, tile
@@ -108,7 +109,8 @@ struct Plan {
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0, ntile_brick = 0;   // single-instance counts
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave
-                          // occupancy, bit 2 workgroups in dispatch order
+                          // occupancy, bit 2 workgroups in dispatch order, bit 3 16 bytes of nodes per lane
+                          // in the population update (buckets up to five orbitals; bits 0 and 1 then unused)
     bool brick_partials = true;   // every instance gets its overlap partials from the brick update
 };
 
@@ -116,7 +118,15 @@ struct Plan {
 // wave-butterfly overlap at the compiler's occupancy with workgroups in dispatch
 // order, FP32 takes the matrix-core overlap at 8 waves per SIMD with the XCD remap.
 inline int default_variant(int precision) { return precision ? 3 : 4; }
-constexpr int N_VARIANTS = 8;
+constexpr int N_VARIANTS = 16;
+// nodes per lane of the wide population update for an element size
+constexpr int wide_nodes(int elem_bytes) { return 16 / elem_bytes; }
+// variants the autotuner times: the eight node-per-lane forms, and the wide form in
+// both workgroup orders when it applies (its bits 0 and 1 change nothing)
+inline bool variant_distinct(int v, int no, bool populations)
+{
+    return v < 8 || (populations && no <= 5 && (v & 3) == 0);
+}
 
 int orbital_bucket(int n_orb);
 
@@ -137,6 +147,8 @@ int launch_stream_collide(const Plan &pl, int parity, hipStream_t st);
 int launch_collapsed_update(const Plan &pl, hipStream_t st);
 int launch_energy_terms(const Plan &pl, hipStream_t st);
 int launch_energy_finalize(const Plan &pl, hipStream_t st);
+// rows j0 .. j0 + *rows_done - 1 of the projected operator into the staging area
+int launch_ham_rows(const Plan &pl, int j0, int *rows_done, hipStream_t st);
 int launch_residual(const Plan &pl, hipStream_t st);
 int launch_residual_finalize(const Plan &pl, hipStream_t st);
 int launch_vext(const Plan &pl, int nnuc, const double *dZR, hipStream_t st);

@@ -686,6 +686,99 @@ __global__ __launch_bounds__(BS) void k_energy_finalize(const InstDesc *__restri
     E[8] = d.scal[SC_RES];
 }
 
+// ---------------------------------------------------- projected operator
+
+// Rows of the relaxation operator projected on the orthonormalised orbitals,
+// H_jk = <psi_hat_j | K_h psi_hat_k + S_chi(V psi_hat_k)>: its diagonal is eps_j,
+// its eigenvalues are the Ritz values on the orbitals' span (they do not depend
+// on rotations inside the span, so nearly degenerate levels are told apart
+// before the orbitals have stopped mixing).  One launch takes rows j0 ..
+// j0 + ham_rows(NO) - 1 into the energy partial array (column r NO + k = row
+// j0 + r, column k).
+template <int NO>
+__host__ __device__ constexpr int ham_rows()
+{
+    return NO < padded_cols(2 * NO + NEBASE) / NO ? NO : padded_cols(2 * NO + NEBASE) / NO;
+}
+
+template <typename T, int NO>
+__global__ __launch_bounds__(BS) void k_ham_terms(const InstDesc *__restrict__ descs, const int2 *__restrict__ tiles,
+                                                  int j0)
+{
+    constexpr int RB = ham_rows<NO>();
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int n = orbitals<NO>(d);
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const int s = tr.tile * BS + threadIdx.x;
+    double v[RB * NO];
+#pragma unroll
+    for (int q = 0; q < RB * NO; ++q) v[q] = 0.0;
+    if (s < d.nsite) {
+        const size_t N = (size_t)d.nsite;
+        const T *ph = (const T *)d.psihat;
+        const double *Vd = d.Vd;
+        const int x = s % nx, yz = s / nx, y = yz % ny, z = yz / ny;
+        double su[NO], sv[NO], u0[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            su[k] = 0.0;
+            sv[k] = 0.0;
+            u0[k] = (k < n) ? (double)ph[(size_t)k * N + s] : 0.0;
+        }
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const int vx = VX(p), vy = VY(p), vz = VZ(p);
+            const bool ok = (unsigned)(x - vx) < (unsigned)nx && (unsigned)(y - vy) < (unsigned)ny &&
+                            (unsigned)(z - vz) < (unsigned)nz;
+            if (ok) {
+                const int src = s - (vx + nx * (vy + ny * vz));
+                const double vn = Vd[src];
+#pragma unroll
+                for (int k = 0; k < NO; ++k) {
+                    if (k < n) {
+                        const double u = (double)ph[(size_t)k * N + src];
+                        su[k] += d.xi[p] * u;
+                        sv[k] += d.chi[p] * vn * u;
+                    }
+                }
+            }
+        }
+        const double kfac = -1.0 / (d.D * d.h * d.h);
+        double w[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) w[k] = kfac * (su[k] - u0[k]) + sv[k];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int j = j0 + r;
+            double uj = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < NO; ++jj)
+                if (jj == j) uj = u0[jj];
+#pragma unroll
+            for (int k = 0; k < NO; ++k) v[r * NO + k] = uj * w[k];
+        }
+    }
+    block_sum_store(v, RB * NO, d.e_part + tr.tile, d.ntile);
+}
+
+// Totals of the rows taken by k_ham_terms, times h^3, into the staging area:
+// stage[j n + k] = H_jk for j0 <= j < j0 + rb, k < n.
+__global__ __launch_bounds__(BS) void k_ham_finalize(const InstDesc *__restrict__ descs, const int *__restrict__ list,
+                                                     int j0, int no, int rb)
+{
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
+    const int n = d.n_orb;
+    __shared__ double tot[2 * MAXO + NEBASE + RCH];
+    if (!reduce_columns(d.e_part, d.ntile, rb * no, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, tot)) return;
+    __syncthreads();
+    for (int q = threadIdx.x; q < rb * no; q += BS) {
+        const int j = j0 + q / no, k = q % no;
+        if (j < n && k < n) d.stage[(size_t)j * n + k] = tot[q] * d.h3;
+    }
+}
+
 // ----------------------------------------------------------------- forces
 
 // Per-node Hellmann-Feynman terms of the Born-Oppenheimer forces: for nuclei
@@ -947,6 +1040,20 @@ int launch_energy_terms(const Plan &pl, hipStream_t st)
     });
 }
 
+int launch_ham_rows(const Plan &pl, int j0, int *rows_done, hipStream_t st)
+{
+    return dispatch_tn(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        constexpr int RB = ham_rows<TG::NO>();
+        k_ham_terms<typename TG::T, TG::NO><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site, j0);
+        int e = (int)hipGetLastError();
+        if (e) return e;
+        k_ham_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst, j0, TG::NO, RB);
+        *rows_done = RB;
+        return (int)hipGetLastError();
+    });
+}
+
 int launch_energy_finalize(const Plan &pl, hipStream_t st)
 {
     k_energy_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
@@ -965,6 +1072,7 @@ int launch_stage_orbitals(const Plan &pl, hipStream_t st)
 int launch_gather(const double *const *scal, int count, int width, double *dst, hipStream_t st)
 {
     if (count <= 0) return 0;
+    if (!scal || !dst) return (int)hipErrorInvalidValue;   // no table built for these members
     k_gather<<<count, 32, 0, st>>>(scal, count, width, dst);
     LAUNCH_CHECK();
 }

@@ -21,6 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbks.so")
 
 LBKS_OK, LBKS_NOT_CONVERGED = 0, 1
+N_VARIANTS = 16           # update-kernel variants (bit 3: 16 bytes of nodes per lane in the population update)
 LBKS_E_INVAL, LBKS_E_NOMEM, LBKS_E_HIP, LBKS_E_NUMERIC, LBKS_E_STATE = -1, -2, -3, -4, -5
 LBKS_ORTHO_GS, LBKS_ORTHO_W = 0, 1
 LBKS_XC_NONE, LBKS_XC_X, LBKS_XC_X_LYPLOCAL, LBKS_XC_X_PZ81, LBKS_XC_B88_LYP = 0, 1, 2, 3, 4
@@ -71,6 +72,7 @@ SIGNATURES = {
     "lbks_energy": (c_int32, [c_void_p, POINTER(lbks_energies)]),
     "lbks_orbitals": (c_int32, [c_void_p, POINTER(c_double), c_size_t, POINTER(c_double), c_size_t]),
     "lbks_forces": (c_int32, [c_void_p, POINTER(c_double), c_size_t]),
+    "lbks_hamiltonian": (c_int32, [c_void_p, POINTER(c_double), c_size_t]),
     "lbks_destroy": (None, [c_void_p]),
     "lbks_last_error": (c_char_p, [c_void_p]),
     "lbks_set_potential": (c_int32, [c_void_p, POINTER(c_double)]),
@@ -204,6 +206,18 @@ def lbks_forces(ctx, n_nuc):
     return F[:n_nuc]
 
 
+def lbks_hamiltonian(ctx, n_orb):
+    """Projected relaxation operator H_jk (n_orb x n_orb, FP64) of the current state."""
+    H = np.zeros((int(n_orb), int(n_orb)))
+    _check(ctx, load().lbks_hamiltonian(ctx, _dptr(H), H.size))
+    return H
+
+
+def ritz_values(H):
+    """Ascending real parts of the eigenvalues of a projected operator."""
+    return np.sort(np.linalg.eigvals(np.asarray(H)).real)
+
+
 def lbks_destroy(ctx):
     if ctx:
         load().lbks_destroy(ctx)
@@ -263,6 +277,13 @@ class Solver:
         self._keep = []
         dev = None
         if use_torch:
+            if stream is None:
+                # a stream of its own: the caching allocator then tags this context's
+                # blocks to the stream its kernels run on, so no block is handed out
+                # while work of another stream may still use it
+                import torch
+                stream = torch.cuda.Stream(device=device)      # default priority
+                stream.wait_stream(torch.cuda.current_stream(device))
             dev, self._keep = torch_device_binding(device, stream, use_allocator)
         self.p = p
         self.ctx = lbks_create(p, dev)
@@ -300,6 +321,11 @@ class Solver:
     def orbitals(self):
         return lbks_orbitals(self.ctx)
 
+    def hamiltonian(self):
+        """(H, Ritz values) of the current state: H_jk = <psi_hat_j|K_h psi_hat_k + S_chi(V psi_hat_k)>."""
+        H = lbks_hamiltonian(self.ctx, self.n_orb)
+        return H, ritz_values(H)
+
     def device_bytes(self) -> int:
         return load().lbks_device_bytes(self.ctx)
 
@@ -316,10 +342,12 @@ class Solver:
         """Pick the fastest update-kernel variant on the current state; returns
         (variant, per-variant ms or None when the process cache answered)."""
         ch = c_int32()
-        ms = (c_double * 8)()
+        ms = (c_double * N_VARIANTS)()
         _check(self.ctx, load().lbks_autotune(self.ctx, int(reps), 1 if force else 0, ctypes.byref(ch), ms))
         times = list(ms)
-        return ch.value, (None if times[0] < 0 else times)
+        if all(t < 0 for t in times):
+            return ch.value, None                     # the process cache answered
+        return ch.value, [None if t < 0 else t for t in times]
 
     def kernel_time(self):
         ms = c_double()

@@ -29,6 +29,8 @@ class PointResult:
     eps: List[float]
     steps: int
     status: int
+    ritz: Optional[List[float]] = None          # with ServeConfig.detail: Ritz values of the projected operator
+    rho_sub4: Optional[np.ndarray] = None       # with ServeConfig.detail: density on every fourth node per axis
 
 
 @dataclass
@@ -63,6 +65,7 @@ class ServeConfig:
     stop_checks: int = FP32_RULE["stop_checks"]
     chunks_per_call: int = 2        # lattice steps between admissions = chunks_per_call * check_every
     max_steps_per_point: int = 20000
+    detail: bool = False            # also record Ritz values and a coarse density per point (for checks)
 
 
 def point_params(system, cfg: ServeConfig) -> lbks.lbks_params:
@@ -74,6 +77,20 @@ def point_bytes(system, cfg: ServeConfig) -> int:
     """Device bytes one slot for this system holds (0 if its parameters are invalid)."""
     p = point_params(system, cfg)
     return int(lbks.load().lbks_estimate_bytes(lbks.ctypes.byref(p)))
+
+
+def point_result(s: "lbks.Solver", system, steps: int, rc: int, cfg: ServeConfig) -> PointResult:
+    """Result of a finished point (energies; with cfg.detail the Ritz values and
+    the density on every fourth node)."""
+    e = s.energy()
+    out = PointResult(e["e_total"], list(e["eps"]), steps, rc)
+    if cfg.detail:
+        _, ritz = s.hamiltonian()
+        _, rho = s.orbitals()
+        nx, ny, nz = system.dims
+        out.ritz = [float(x) for x in ritz]
+        out.rho_sub4 = rho.reshape(nz, ny, nx)[::4, ::4, ::4].copy()
+    return out
 
 
 def solve_alone(request, cfg: ServeConfig) -> List[PointResult]:
@@ -92,8 +109,7 @@ def solve_alone(request, cfg: ServeConfig) -> List[PointResult]:
                 steps += k
                 if rc == lbks.LBKS_OK:
                     break
-            e = s.energy()
-            out.append(PointResult(e["e_total"], list(e["eps"]), steps, rc))
+            out.append(point_result(s, sy, steps, rc, cfg))
     finally:
         s.close()
     return out
@@ -163,8 +179,7 @@ class Server:
                 if rc < 0:
                     raise lbks.LbksError(rc, f"request {rid} failed")
                 if rc == lbks.LBKS_OK or a["steps"] >= cfg.max_steps_per_point:
-                    e = s.energy()
-                    a["res"].points.append(PointResult(e["e_total"], list(e["eps"]), a["steps"], rc))
+                    a["res"].points.append(point_result(s, a["req"].points[a["point"]], a["steps"], rc, cfg))
                     a["point"] += 1
                     a["steps"] = 0
                     if a["point"] < len(a["req"].points):

@@ -93,3 +93,31 @@ def test_batch_stopping_rule_per_member(L, rule):
         e = s.energy()
         assert e["e_total"] == e_a["e_total"], sy.name
     b.close()
+
+
+def test_batch_relax_without_steps_reports_statuses(L):
+    """A relax that steps nothing still reports every member: max_steps = 0, a
+    member without a potential, and a member attached after the last build all
+    read back through a pointer table built for the current members."""
+    say("batch relax without steps")
+    b = L.Batch()
+    with_nuc = b.add_system(I.he_atom().scaled(12, h=0.4))
+    without = b.add_system(I.he_atom().scaled(12, h=0.4), set_nuclei=False)
+    st, steps = b.relax(0, dE_tol=0.0, check_every=10)
+    assert st == [L.LBKS_NOT_CONVERGED, L.LBKS_E_STATE] and steps == [0, 0]
+    st, steps = b.relax(5, dE_tol=0.0, check_every=10)
+    assert st == [L.LBKS_NOT_CONVERGED, L.LBKS_E_STATE] and steps == [5, 0]
+    late = b.add_system(I.atom(3, 12, h=0.4, seed=9))          # attached after the last build
+    st, steps = b.relax(0, dE_tol=0.0, check_every=10)
+    assert st == [L.LBKS_NOT_CONVERGED, L.LBKS_E_STATE, L.LBKS_NOT_CONVERGED] and steps == [0, 0, 0]
+    b.remove(without)
+    without.close()
+    st, steps = b.relax(0, dE_tol=0.0, check_every=10)
+    assert st == [L.LBKS_NOT_CONVERGED, L.LBKS_NOT_CONVERGED] and steps == [0, 0]
+    only = L.Batch()
+    only.add_system(I.he_atom().scaled(12, h=0.4), set_nuclei=False)
+    st, steps = only.relax(3, dE_tol=1e-8, check_every=1)
+    assert st == [L.LBKS_E_STATE] and steps == [0]
+    assert np.isfinite(with_nuc.energy()["e_total"]) and np.isfinite(late.energy()["e_total"])
+    only.close()
+    b.close()

@@ -342,10 +342,11 @@ def test_full_size_ne_fp64_two_steps(L):
     s.close()
 
 
-@pytest.mark.parametrize("variant", list(range(8)))
+@pytest.mark.parametrize("variant", list(range(8)) + [8, 12])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_update_kernel_variants_match_oracle(L, variant, prec):
-    """Every autotuner variant of the update kernels computes the same step."""
+    """Every autotuner variant of the update kernels computes the same step (20^3
+    is 31.25 node tiles: the wide form's last lane holds a partial run)."""
     system = I.ne_atom().scaled(20)
     say("variant", variant, "precision", prec)
     s, o = make_pair(L, system, precision=prec)
@@ -378,6 +379,60 @@ def test_dispatch_order_bit_changes_no_result(L, prec):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("case", ["ragged_19", "w_mode", "non_cubic_fp32", "omega0.8_3orb", "batch"])
+def test_wide_population_update_matches_oracle(L, case):
+    """The wide population update (variant bit 3) on grids whose node count is not a
+    multiple of the nodes per lane (19^3 = 6859; 30 x 22 x 13 in FP32 has rows of 30
+    nodes, so runs cross rows), in the paper's orthogonalisation mode, at omega != 1
+    with three orbitals, and as batch members next to node-per-lane members."""
+    say("wide", case)
+    if case == "batch":
+        systems = [(I.ne_atom().scaled(19), dict(precision=0)), (I.atom(5, 17, h=0.35, seed=4), dict(precision=1)),
+                   (I.he_atom().scaled(17), dict(precision=0))]
+        b = L.Batch()
+        members = []
+        for k, (sy, kw) in enumerate(systems):
+            m = b.add(L.params_for(sy, init=L.LBKS_INIT_USER, **kw))
+            m.set_nuclei(sy.Z, sy.R)
+            m.set_orbitals(sy.psi0())
+            m.set_variant(8 if k != 2 else 4)
+            members.append(m)
+        b.relax(12, dE_tol=0.0, check_every=6)
+        for (sy, kw), m in zip(systems, members):
+            s = L.Solver(L.params_for(sy, init=L.LBKS_INIT_USER, **kw))
+            s.set_nuclei(sy.Z, sy.R)
+            s.set_orbitals(sy.psi0())
+            s.set_variant(m.variant())
+            s.relax(12)
+            assert np.array_equal(s.orbitals()[0], m.orbitals()[0]), sy.name   # batch == alone, bit for bit
+            s.close()
+            if kw["precision"] == 0:
+                o = O.oracle_for(sy)
+                for _ in range(12):
+                    o.step()
+                compare_state(m, o, 1e-10, 1e-10)
+        b.close()
+        return
+    system, kw = {"ragged_19": (I.ne_atom().scaled(19), {}),
+                  "w_mode": (I.ne_atom().scaled(19), dict(ortho=1)),
+                  "non_cubic_fp32": (non_cubic(I.ne_atom()), dict(precision=1)),
+                  "omega0.8_3orb": (I.atom(6, 18, h=0.3, seed=12), dict(omega=0.8))}[case]
+    s, o = make_pair(L, system, **kw)
+    s.set_variant(12)
+    s.relax(25)
+    for _ in range(25):
+        o.step()
+    if kw.get("precision"):
+        _, rho = s.orbitals()
+        _, rho_o = o.state()
+        assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-5 * np.linalg.norm(rho_o)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-6)
+    else:
+        compare_state(s, o, 1e-10, 1e-10)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
 def test_autotune_leaves_the_trajectory_unchanged(L):
     system = I.ne_atom().scaled(20)
     say("autotune")
@@ -386,7 +441,10 @@ def test_autotune_leaves_the_trajectory_unchanged(L):
     for _ in range(5):
         o.step()
     v, times = s.autotune(reps=3, force=True)
-    assert 0 <= v < 8 and times is not None and len(times) == 8 and all(t > 0 for t in times)
+    assert 0 <= v < 16 and times is not None and len(times) == 16
+    assert all(times[k] > 0 for k in list(range(8)) + [8, 12])          # the distinct variants were timed
+    assert all(times[k] is None for k in (9, 10, 11, 13, 14, 15))       # the others are the same kernels
+    assert times[v] == min(t for t in times if t is not None)
     assert s.variant() == v
     v2, times2 = s.autotune(reps=3, force=False)       # cached
     assert v2 == v and times2 is None
@@ -405,3 +463,31 @@ def test_autotune_leaves_the_trajectory_unchanged(L):
         oc.step()
     compare_state(c, oc, 1e-10, 1e-10)
     c.close()
+
+
+@pytest.mark.parametrize("Z,n,kw", [(2, 16, {}), (10, 20, {}), (10, 20, dict(precision=1)), (12, 16, {}),
+                                    (32, 16, {}), (10, 18, dict(xc=4))],
+                         ids=["1orb", "5orb", "5orb_fp32", "6orb", "16orb", "5orb_gga"])
+def test_projected_operator_matches_oracle(L, Z, n, kw):
+    """lbks_hamiltonian: H_jk = <psi_hat_j|K_h psi_hat_k + S_chi(V psi_hat_k)> after
+    the same steps, every entry against the oracle's (FP64 1e-10 relative; FP32
+    bulk against the FP64 oracle 1e-5 Ha), its diagonal equal to the eps_j of
+    lbks_energy, and its Ritz values against the oracle's."""
+    system = I.atom(Z, n, h=0.3, softening=0.3, seed=13) if Z != 10 else I.ne_atom().scaled(n)
+    say("projected operator", Z, n, kw)
+    s, o = make_pair(L, system, **kw)
+    if kw.get("xc") == 4:                      # the gradient-corrected functional needs a smooth start
+        psi0 = lda_relaxed_orbitals(system)
+        s.set_orbitals(psi0)
+        o.set_orbitals(psi0)
+    s.relax(15)
+    for _ in range(15):
+        o.step()
+    H, ritz = s.hamiltonian()
+    Ho, ritz_o = o.hamiltonian()
+    tol = 1e-5 if kw.get("precision") else 1e-10 * max(1.0, np.abs(Ho).max())
+    assert np.max(np.abs(H - Ho)) <= tol, np.max(np.abs(H - Ho))
+    assert np.max(np.abs(ritz - ritz_o)) <= tol
+    e = s.energy()
+    assert np.allclose(np.diag(H), e["eps"][:system.n_orb], rtol=0, atol=1e-12 * max(1.0, np.abs(H).max()))
+    s.close()

@@ -230,3 +230,51 @@ def test_nuclear_repulsion_closed_form(oracle_mod):
     o.set_nuclei([3.0, 2.0, 1.0], [[0, 0, 0], [1.7, 0, 0], [0, 0, 2.5]])
     d23 = math.hypot(1.7, 2.5)
     assert abs(o.e_nn - (6.0 / 1.7 + 3.0 / 2.5 + 2.0 / d23)) < 1e-14
+
+
+@pytest.mark.parametrize("Z", [1.0, 2.0])
+def test_radial_reference_reaches_hydrogen_like_closed_form(Z):
+    """The softened radial level E(a) used above tends to the hydrogen-like -Z^2/2 as
+    a -> 0: E(a) = -Z^2/2 - 2 Z^4 a^2 ln a + c a^2 + o(a^2) (first-order shift of the
+    1s level), so a fit of E0 + a^2 (c1 + c2 ln a) through a = 0.008, 0.004, 0.002
+    gives E0 = -Z^2/2 and c2 = -2 Z^4.  With the 3-D pin above (the oracle's level
+    extrapolated in h equals this radial level at fixed a, Z = 4, a = 0.5) this ties
+    the oracle to the closed form."""
+    rows, rhs = [], []
+    for a in (0.008, 0.004, 0.002):
+        rows.append([1.0, a * a, a * a * math.log(a)])
+        rhs.append(radial_ground_level(Z, a, R=14.0 / Z))
+    e0, c1, c2 = np.linalg.solve(np.array(rows), np.array(rhs))
+    assert abs(e0 + 0.5 * Z * Z) < 1e-6, e0
+    assert abs(c2 / (-2.0 * Z ** 4) - 1.0) < 0.05
+    # the level rises monotonically with the softening
+    assert radial_ground_level(Z, 0.1, R=14.0 / Z) > radial_ground_level(Z, 0.01, R=14.0 / Z) > -0.5 * Z * Z
+
+
+def test_total_energy_double_counting_identity(oracle_mod):
+    """E_total's composition against the eigenvalues: with eps_j = <psi_j|K_h psi_j>
+    + <psi_j|S_chi(V psi_j)> and V = V_ext + V_H + v_xc,
+      E_total = sum_j occ_j eps_j - E_H - <v_xc|rho> + E_x + E_c + E_NN - X,
+      X = sum_j occ_j <psi_j|(S_chi - I)(V psi_j)>  (the source's smearing),
+    holds exactly for any state (here a few steps into an SCF run with Hartree and
+    xc on).  S_chi is built here as a sparse matrix; a wrong factor on E_H, or
+    eps_xc and v_xc swapped, breaks it by far more than rounding."""
+    O = oracle_mod
+    from paper_1507_07666_amd import inputs as I
+    from test_oracle_spectral import sparse_stencil
+    system = I.ne_atom().scaled(14, h=0.35)
+    o = O.oracle_for(system)
+    for _ in range(25):
+        o.step()
+    e = o.energies(converge_poisson=True)
+    psihat, rho = o.state()
+    V, (ex, ec, vx, vc) = o.potential(rho)
+    v, _, _, chi = O.lattice()
+    Schi = sparse_stencil(system.dims, v, chi)
+    h3 = system.h ** 3
+    X = sum(o.occ[j] * h3 * psihat[j] @ (Schi @ (V * psihat[j]) - V * psihat[j]) for j in range(system.n_orb))
+    vxc_rho = h3 * np.dot(vx + vc, rho)
+    rhs = np.dot(o.occ, e.eps) - e.e_hartree - vxc_rho + e.e_x + e.e_c + e.e_nn - X
+    assert abs(e.e_total - rhs) < 1e-10 * abs(e.e_total), (e.e_total, rhs)
+    assert abs(X) > 1e-6                                   # the smearing term is really there
+    assert abs(e.e_hartree) > 1.0 and abs(vxc_rho - e.e_x - e.e_c) > 0.1   # and the others matter

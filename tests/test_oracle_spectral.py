@@ -224,3 +224,131 @@ def test_population_operator_dominant_mode(oracle_mod, omega):
     assert abs(n_next - lam0.real) < 1e-11
     psihat, _ = o.state()
     assert subspace_distance(psihat.T, psi_ref[:, None]) < 1e-8
+
+
+def test_projected_operator_and_ritz_values(oracle_mod):
+    """The oracle's projected operator H_jk = <psi_hat_j|K_h psi_hat_k + S_chi(V psi_hat_k)>
+    equals U^T (I - M) U / dt for the orthonormal basis U = h^(3/2) psi_hat of any
+    state (at omega = 1, dt = D h^2 makes K_h = (I - S_xi)/dt), written here with the
+    dense M; rotating the basis inside its span leaves its eigenvalues (the Ritz
+    values) unchanged while its diagonal changes; on the relaxed subspace the Ritz
+    values are M's dominant eigenvalues mapped to (1 - lambda_k)/dt."""
+    O = oracle_mod
+    dims, h, n_orb = (12, 12, 12), 0.3, 4
+    V = ho_potential(dims, h, 2.0)
+    M, dt = relaxation_matrix(dims, h, V, O)
+    o = fixed_potential_oracle(O, dims, h, n_orb, V, seed=4)
+    for _ in range(5):
+        o.step()
+    psihat, _ = o.state()
+    U = psihat.T * h ** 1.5
+    H, ritz = o.hamiltonian(converge_poisson=False)
+    Href = U.T @ ((np.eye(M.shape[0]) - M) @ U) / dt
+    assert np.allclose(H, Href, rtol=0, atol=1e-10 * np.abs(Href).max())
+    assert np.allclose(np.diag(H), o.energies(converge_poisson=False).eps, rtol=0, atol=1e-12)
+    # rotation inside the span (GS of an orthonormal set is the identity)
+    th = 0.7
+    R = np.eye(n_orb)
+    R[1, 1] = R[2, 2] = np.cos(th)
+    R[1, 2], R[2, 1] = -np.sin(th), np.sin(th)
+    o2 = fixed_potential_oracle(O, dims, h, n_orb, V, seed=4)
+    o2.set_orbitals(R.T @ psihat)
+    H2, ritz2 = o2.hamiltonian(converge_poisson=False)
+    assert np.abs(np.diag(H2) - np.diag(H)).max() > 1e-3
+    assert np.allclose(ritz2, ritz, rtol=0, atol=1e-11)
+    # relaxed subspace: the dominant eigenvalues of M
+    ev = np.sort(np.linalg.eigvals(M).real)[::-1]
+    steps = int(np.ceil(np.log(1e-8) / np.log(ev[n_orb] / ev[n_orb - 1])))
+    for _ in range(steps):
+        o.step()
+    _, ritz3 = o.hamiltonian(converge_poisson=False)
+    assert np.allclose(ritz3, np.sort((1.0 - ev[:n_orb]) / dt), rtol=0, atol=1e-9)
+
+
+def test_field_step_is_the_moment_of_the_population_step(oracle_mod):
+    """At omega = 1 the oracle's field step psi <- S_xi psi_hat - dt S_chi(V psi_hat)
+    gives the moment of the population step (Hartree and xc on, several orbitals,
+    ragged grid), so both relax to the same fixed point; the sums differ only in
+    rounding order."""
+    O = oracle_mod
+    from paper_1507_07666_amd import inputs as I
+    system = I.ne_atom().scaled(15)
+    a, b = O.oracle_for(system), O.oracle_for(system)
+    for _ in range(3):
+        a.step()
+        b.step()
+    a.step()
+    b.step_fields()
+    pa, pb = a.moment(), b.moment()
+    assert np.max(np.abs(pa - pb)) <= 1e-14 * np.max(np.abs(pa))
+    for _ in range(4):                      # and back: a population step after field steps
+        b.step_fields()
+        a.step()
+    b.step()
+    a.step()
+    assert np.max(np.abs(a.moment() - b.moment())) <= 1e-13 * np.max(np.abs(pa))
+    ea, eb = a.energies(), b.energies()
+    assert abs(ea.e_total - eb.e_total) <= 1e-12 * abs(ea.e_total)
+    with pytest.raises(ValueError):
+        O.oracle_for(system, omega=0.8).step_fields()
+
+
+def w_mode_reference_step(f, xi, chi, v, V, dt, omega, dims, h):
+    """The paper-literal orthogonalisation source written out with numpy (independent
+    of the oracle): psi_j = sum_p f_jp, S_jl = <psi_j|psi_l> = h^3 sum psi_j psi_l,
+    n_j = sqrt(S_jj), psi_hat_j = psi_j / n_j, Lambda_jl =
+    S_jl / (n_j n_l), psi*_j = psi_hat_j - sum_{l<j} Lambda_jl psi_hat_l,
+    post = (1 - omega) f_jp / n_j + omega xi_p psi*_j - dt chi_p V psi_hat_j,
+    then streamed with zero inflow."""
+    nx, ny, nz = dims
+    n = f.shape[0]
+    psi = f.sum(1)
+    S = h ** 3 * (psi @ psi.T)
+    nrm = np.sqrt(np.diag(S))
+    hat = psi / nrm[:, None]
+    lam = S / np.outer(nrm, nrm)
+    star = hat.copy()
+    for j in range(n):
+        for l in range(j):
+            star[j] -= lam[j, l] * hat[l]
+    out = np.zeros_like(f)
+    for j in range(n):
+        for p in range(19):
+            post = ((1 - omega) * f[j, p] / nrm[j] + omega * xi[p] * star[j] - dt * chi[p] * V * hat[j])
+            post = post.reshape(nz, ny, nx)
+            vx, vy, vz = v[p]
+            dst = out[j, p].reshape(nz, ny, nx)
+            dst[max(vz, 0):nz + min(vz, 0), max(vy, 0):ny + min(vy, 0), max(vx, 0):nx + min(vx, 0)] = \
+                post[max(-vz, 0):nz + min(-vz, 0), max(-vy, 0):ny + min(-vy, 0), max(-vx, 0):nx + min(-vx, 0)]
+    return out
+
+
+@pytest.mark.parametrize("omega", [1.0, 0.8])
+def test_w_mode_on_low_symmetry_potential_follows_the_lagged_projection_map(oracle_mod, omega):
+    """The oracle's W mode on a potential without mirror symmetries (a displaced,
+    anisotropic well plus a random smooth bump) follows the lagged-projection map
+    written out independently, step by step (30 steps, 3 orbitals), and keeps
+    following it near its fixed point (after 600 more steps)."""
+    O = oracle_mod
+    from paper_1507_07666_amd.inputs import node_coords
+    dims, h, n_orb = (9, 10, 11), 0.35, 3
+    nx, ny, nz = dims
+    x, y, z = node_coords(nx, h), node_coords(ny, h), node_coords(nz, h)
+    X, Y, Zc = x[None, None, :], y[None, :, None], z[:, None, None]
+    rng = np.random.default_rng(21)
+    c = rng.uniform(-0.3, 0.3, 3)
+    V = (0.5 * (4.0 * (X - c[0]) ** 2 + 2.2 * (Y - c[1]) ** 2 + 1.1 * (Zc - c[2]) ** 2)
+         + 0.8 * (X - c[0]) * (Y - c[1]) + 0.5 * np.exp(-((X - 0.4) ** 2 + (Y + 0.3) ** 2 + (Zc - 0.2) ** 2))).ravel()
+    o = fixed_potential_oracle(O, dims, h, n_orb, V, seed=5, omega=omega, ortho="w")
+    v, _, xi, chi = O.lattice()
+    f = o.f.copy()
+    for k in range(30):
+        f = w_mode_reference_step(f, xi, chi, v, V, o.prm.dt, omega, dims, h)
+        o.step()
+        assert np.max(np.abs(o.f - f)) <= 1e-12 * np.max(np.abs(f)), k
+    for _ in range(600):
+        o.step()
+    f = o.f.copy()
+    f2 = w_mode_reference_step(f, xi, chi, v, V, o.prm.dt, omega, dims, h)
+    o.step()
+    assert np.max(np.abs(o.f - f2)) <= 1e-12 * np.max(np.abs(f2))
