@@ -244,8 +244,9 @@ int lbks_orbitals(lbks_ctx *ctx, double *psi, size_t n_psi, double *rho, size_t 
 /* Release the context and all its device memory. */
 void lbks_destroy(lbks_ctx *ctx);
 
-/* Message of the last error on `ctx` (or of the last failed lbks_create when
- * ctx is NULL).  Valid until the next call on the same context. */
+/* Message of the last error on `ctx` (or, when ctx is NULL, of the last failed
+ * lbks_create or batch relaxation on this thread).  Valid until the next call on
+ * the same context. */
 const char *lbks_last_error(const lbks_ctx *ctx);
 
 /* ---- extensions ---- */
@@ -334,6 +335,22 @@ int lbks_batch_detach(lbks_batch *b, lbks_ctx *ctx);
 int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
                      int32_t *status, int64_t *steps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): lbks_batch_relax with
+ * the same arguments, results and statuses, whose descriptor, tile and gather
+ * tables go to a fixed device workspace of LBKS_STATIC_WORKSPACE_BYTES inside
+ * the library (one per GPU, held until the process ends) instead of memory the
+ * batch allocates, and whose steps are launched one by one instead of from HIP
+ * graphs.  It calls no device allocation routine; the members' own buffers were
+ * allocated at lbks_create.  The tables are rebuilt in the workspace on every
+ * call.  Every call on one GPU shares that GPU's workspace: calls that overlap
+ * in time on one GPU (other threads, other streams) race and must not be made.
+ * LBKS_E_INVAL (message from lbks_last_error(NULL)) when the tables of the
+ * current members need more than LBKS_STATIC_WORKSPACE_BYTES; LBKS_E_HIP if
+ * the workspace's address cannot be obtained. */
+#define LBKS_STATIC_WORKSPACE_BYTES (2u << 20)
+int lbks_batch_relax_static(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
+                            int32_t *status, int64_t *steps);
 int lbks_batch_size(const lbks_batch *b);
 
 /* The hipStream_t the batch launches on (members must be created on it). */

@@ -88,6 +88,7 @@ struct lbks_batch {
     const double **d_scal = nullptr;    // members' scalar blocks
     uint64_t member_epoch = 0;          // bumped by every attach and detach
     uint64_t table_epoch = ~0ull;       // member_epoch the device tables were built for
+    bool tables_static = false;         // the tables sit in the static workspace (lbks_batch_relax_static)
     bool dirty = true;
     int bparity = 0;                    // population buffer parity within the current plan
     int64_t epoch_steps = 0;            // steps since the plan was built
@@ -1077,8 +1078,10 @@ int batch_enqueue_step(lbks_batch *b, int bp)
 }
 
 // Group the running members, upload their descriptors and tile tables, and
-// capture one step per parity into HIP graphs.
-int batch_build(lbks_batch *b)
+// capture one step per parity into HIP graphs.  With `fixed` the tables go to that
+// device memory of `fixed_cap` bytes instead of the batch's own allocation, and no
+// graph is captured (the steps are launched one by one): nothing is allocated.
+int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
 {
     batch_commit(b);
     batch_destroy_graphs(b);
@@ -1142,7 +1145,13 @@ int batch_build(lbks_batch *b)
     }
     const size_t gather_off = take(sizeof(double) * GATHER_W * std::max(m, 1));
     const size_t scal_off = take(sizeof(double *) * std::max(m, 1));
-    if (off > b->mem_bytes) {
+    if (fixed && off > fixed_cap) {
+        char msg[192];
+        snprintf(msg, sizeof msg, "the batch tables need %zu bytes, more than the %zu-byte static workspace "
+                 "(lbks_batch_relax allocates instead)", off, fixed_cap);
+        return batch_fail(b, LBKS_E_INVAL, msg);
+    }
+    if (!fixed && off > b->mem_bytes) {
         batch_free_mem(b);
         void *p = nullptr;
         if (b->ualloc) p = b->ualloc(off, b->user);
@@ -1152,7 +1161,7 @@ int batch_build(lbks_batch *b)
         b->mem_bytes = off;
     }
     std::vector<char> host(off, 0);
-    char *base = (char *)b->mem;
+    char *base = fixed ? (char *)fixed : (char *)b->mem;
     for (size_t k = 0; k < b->groups.size(); ++k) {
         BatchGroup &g = b->groups[k];
         const Off &o = go[k];
@@ -1207,10 +1216,11 @@ int batch_build(lbks_batch *b)
     b->d_gather = (double *)(base + gather_off);
     b->d_scal = (const double **)(base + scal_off);
     b->table_epoch = b->member_epoch;
-    if (hipMemcpyAsync(b->mem, host.data(), off, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+    b->tables_static = fixed != nullptr;
+    if (hipMemcpyAsync(base, host.data(), off, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return batch_fail(b, LBKS_E_HIP, "batch table upload failed");
-    if (b->use_graph && !b->groups.empty()) {
+    if (!fixed && b->use_graph && !b->groups.empty()) {
         for (int bp = 0; bp < 2; ++bp) {
             if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return batch_fail(b, LBKS_E_HIP, "hipStreamBeginCapture failed");
@@ -1289,11 +1299,20 @@ extern "C" int lbks_batch_detach(lbks_batch *b, lbks_ctx *c)
 
 extern "C" int lbks_batch_size(const lbks_batch *b) { return b ? (int)b->members.size() : 0; }
 
-extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
-                                int32_t *status, int64_t *steps)
+namespace {
+
+// The relaxation of lbks_batch_relax; with `fixed` every table build of this call
+// goes to that workspace (lbks_batch_relax_static).
+int batch_relax_impl(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every, int32_t *status,
+                     int64_t *steps, void *fixed, size_t fixed_cap)
 {
-    if (!b) return LBKS_E_INVAL;
     const int m = (int)b->members.size();
+    bool built = false;                 // tables built during this call
+    auto build = [&]() -> int {
+        const int e = batch_build(b, fixed, fixed_cap);
+        if (!e) built = true;
+        return e;
+    };
     std::vector<int> st(m, LBKS_NOT_CONVERGED);
     std::vector<int64_t> done(m, 0);
     batch_commit(b);
@@ -1310,8 +1329,11 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
     // last build; a relax that stepped nothing (max_steps == 0, no member with a
     // potential) or follows an attach or detach builds the table first.
     auto gather = [&]() -> int {
-        if (!b->d_scal || b->table_epoch != b->member_epoch) {
-            const int e = batch_build(b);
+        // the static workspace is shared by every call on the device: its tables
+        // are trusted only when built in this call
+        if (!b->d_scal || b->table_epoch != b->member_epoch || b->tables_static != (fixed != nullptr) ||
+            (fixed && !built)) {
+            const int e = build();
             if (e) return e;
         }
         if (launch_gather(b->d_scal, m, GATHER_W, b->d_gather, b->stream)) return LBKS_E_HIP;
@@ -1327,7 +1349,7 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
         bool any = false;
         for (int i = 0; i < m; ++i) any |= b->running[i] != 0;
         if (!any) break;
-        if (b->dirty && (rc = batch_build(b))) break;
+        if (b->dirty && (rc = build())) break;
         const int64_t n = std::min<int64_t>(check_every, max_steps - t);
         for (int64_t k = 0; k < n; ++k) {
             if (b->exec[b->bparity]) {
@@ -1379,7 +1401,54 @@ extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol,
         if (status) status[i] = st[i];
         if (steps) steps[i] = done[i];
     }
+    if (rc) g_create_error = b->err;    // lbks_last_error(NULL) reports a failed batch call
     return rc ? rc : m;
+}
+
+// Fixed device workspace of lbks_batch_relax_static.  Each GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[LBKS_STATIC_WORKSPACE_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;    // device -> address of that device's copy of `scratch`
+
+// Address of `scratch` on device `dev`, which must be the current device (looked
+// up once per device).
+int scratch_address(int dev, void **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return 0;
+    }
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBKS_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int lbks_batch_relax(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
+                                int32_t *status, int64_t *steps)
+{
+    if (!b) return LBKS_E_INVAL;
+    return batch_relax_impl(b, max_steps, dE_tol, check_every, status, steps, nullptr, 0);
+}
+
+extern "C" int lbks_batch_relax_static(lbks_batch *b, int64_t max_steps, double dE_tol, int32_t check_every,
+                                       int32_t *status, int64_t *steps)
+{
+    if (!b) return LBKS_E_INVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return LBKS_E_HIP;
+    void *ws = nullptr;
+    if (scratch_address(b->device, &ws)) {
+        g_create_error = "hipGetSymbolAddress of the static workspace failed";
+        return LBKS_E_HIP;
+    }
+    return batch_relax_impl(b, max_steps, dE_tol, check_every, status, steps, ws, LBKS_STATIC_WORKSPACE_BYTES);
 }
 
 extern "C" void lbks_batch_destroy(lbks_batch *b)

@@ -91,6 +91,8 @@ SIGNATURES = {
     "lbks_batch_detach": (c_int32, [c_void_p, c_void_p]),
     "lbks_batch_relax": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int32),
                                    POINTER(c_int64)]),
+    "lbks_batch_relax_static": (c_int32, [c_void_p, c_int64, c_double, c_int32, POINTER(c_int32),
+                                          POINTER(c_int64)]),
     "lbks_batch_size": (c_int32, [c_void_p]),
     "lbks_batch_stream": (c_void_p, [c_void_p]),
     "lbks_batch_destroy": (None, [c_void_p]),
@@ -407,13 +409,17 @@ class Batch:
         _check(s.ctx, load().lbks_batch_detach(self.handle, s.ctx))
         self.solvers.remove(s)
 
-    def relax(self, max_steps, dE_tol=0.0, check_every=100):
+    def relax(self, max_steps, dE_tol=0.0, check_every=100, static=False):
+        """Advance every member; static=True takes lbks_batch_relax_static (tables in
+        the library's fixed device workspace, no allocation, no graphs)."""
         m = len(self.solvers)
         st = (c_int32 * max(1, m))()
         steps = (c_int64 * max(1, m))()
-        rc = load().lbks_batch_relax(self.handle, int(max_steps), float(dE_tol), int(check_every), st, steps)
+        fn = load().lbks_batch_relax_static if static else load().lbks_batch_relax
+        rc = fn(self.handle, int(max_steps), float(dE_tol), int(check_every), st, steps)
         if rc < 0:
-            raise LbksError(rc, "lbks_batch_relax failed")
+            msg = load().lbks_last_error(None)
+            raise LbksError(rc, (msg.decode() if msg else "") or "batch relaxation failed")
         return list(st[:m]), list(steps[:m])
 
     def close(self):
