@@ -112,8 +112,23 @@ typedef struct lbks_params {
     int32_t scheme;          /* LBKS_SCHEME_* */
     int32_t stop_checks;     /* stopping rule of lbks_relax: consecutive passing checks needed (0, 1: one) */
     double deps_tol;         /* > 0: a check also needs |change of sum_j eps_j| < deps_tol */
-    int32_t reserved[4];     /* must be zero */
+    int32_t hermite;         /* order of the Hermite expansion of the equilibrium and source
+                                weights: 2 (0 means 2) or 4 (see LBKS_HERMITE_4) */
+    int32_t reserved[3];     /* must be zero */
 } lbks_params;
+
+/* Fourth-order Hermite weights (params.hermite = 4; the paper uses fourth order
+ * in its He run, section Results): on the D3Q19 velocities the equilibrium
+ * weights also match the mixed fourth moment of a Gaussian of variance D,
+ *   sum_p xi_p = 1, sum xi_p v_a v_b = D delta_ab, sum xi_p v_x^2 v_y^2 = D^2,
+ *   i.e. xi = 1 - 3D + 3D^2 (rest), D/2 - D^2 (faces), D^2/4 (edges),
+ * equal to the second-order weights at D = c_s^2 = 1/3, and the potential
+ * source has no second or mixed fourth moment,
+ *   sum chi_p = 1, sum chi_p v_a v_b = 0, sum chi_p v_x^2 v_y^2 = 0,
+ * which on D3Q19 leaves chi = 1 on the rest velocity: the potential acts at the
+ * node, so the relaxation operator is symmetric and the fixed point variational.
+ * Stable for D in (0, 1/2] (the symbol of S_xi stays non-negative). */
+#define LBKS_HERMITE_4 4
 
 /* Device binding.  `stream` is a hipStream_t (NULL: the library creates one).
  * `alloc`/`free` (both or neither) route every device allocation of the
@@ -152,7 +167,8 @@ int lbks_params_default(lbks_params *p);
  * Rejects (LBKS_E_INVAL) parameters outside the stable region: omega in
  * (0, 2), D in (0, 7/18] (the relaxation stencil keeps a non-negative symbol),
  * n_elec outside (2 (n_orb - 1), 2 n_orb] (or != n_orb for the fully
- * spin-polarised functional), a nonzero reserved field, or the collapsed scheme at
+ * spin-polarised functional), hermite not 0, 2 or 4 (D up to 1/2 with 4), a
+ * nonzero reserved field, or the collapsed scheme at
  * omega != 1.  LBKS_E_NOMEM if the device memory cannot be allocated.
  * The context owns its device memory until lbks_destroy. */
 int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ctx **out);
@@ -250,6 +266,84 @@ void lbks_destroy(lbks_ctx *ctx);
 const char *lbks_last_error(const lbks_ctx *ctx);
 
 /* ---- extensions ---- */
+
+/* The sequential order of the time-dependent Gram-Schmidt procedure (the
+ * closing remark on eq. KSLB-2, section "The kinetic approach to Kohn-Sham
+ * theory": evolve psi_0 to its ground state, then psi_1, and so on), on the
+ * omega = 1 field update (params.scheme = LBKS_SCHEME_COLLAPSED, Gram-Schmidt):
+ * in stage k only orbital k takes lattice steps, the others keep their fields;
+ * every orbital is orthonormalised in order each step (so orbital k is projected
+ * against the converged lower ones) and the density is that of all orbitals in
+ * their current state.  Stage k ends when eps_k changed by less than deps_tol
+ * over check_every steps; a sweep runs the stages k = 0 .. n_orb - 1, and sweeps
+ * repeat until the total energy changed by less than dE_tol from the previous
+ * sweep (the later orbitals' density drives V in the earlier stages, so one
+ * sweep is not self-consistent).  Returns LBKS_OK, LBKS_NOT_CONVERGED (max_steps
+ * or max_sweeps reached), or an error; *steps_done and *sweeps_done (may be
+ * NULL) receive the counts.  LBKS_E_INVAL for another scheme or orthogonalisation
+ * or non-positive tolerances; LBKS_E_STATE without a potential, for a batch
+ * member or during concurrent dynamics. */
+int lbks_relax_sequential(lbks_ctx *ctx, int64_t max_steps, double dE_tol, double deps_tol, int32_t check_every,
+                          int32_t max_sweeps, int64_t *steps_done, int32_t *sweeps_done);
+
+/* ---- concurrent dynamics: electrons and nuclei moved together in real time
+ * (section "Concurrent Dynamics", eq. KSLBCD) ----
+ *
+ * The orbitals become complex fields advanced by the two-step time-centred
+ * lattice scheme, in this reading of eq. KSLBCD: the populations are at
+ * equilibrium with their moment (f_jp = xi_p psi_j, the omega = 1 relaxation),
+ * so the scheme advances the orbitals themselves,
+ *   psi_j^{n+1} = psi_j^{n-1} - 2 i h (H - E_j) psi_j^n,  H u = K_h u + S_chi(V u),
+ * with K_h u = -(S_xi u - u) / (D dx^2) and V = V_ext + V_H + v_xc of the
+ * density sum_j occ_j |psi_j^n|^2, rebuilt before every step (multipole
+ * boundary and params.poisson_sweeps warm-started red/black sweeps).  H is the
+ * operator whose steady state lbks_relax reaches, so a relaxed ground state is
+ * stationary.  The paper's U_jp = kappa w_p q_p E_j phi_j, which keeps the
+ * energy at E_j, is read as each orbital's energy reference E_j (its eps_j at
+ * the start): a global phase per orbital, which leaves densities, energies and
+ * forces unchanged and stops the two-step scheme's parasitic mode from growing
+ * through the density-dependent V.  Once the nuclei move, the orbitals' energies
+ * drift away from E_j and that mode grows again; restarts remove it: every
+ * restart_every-th step re-centres E_j on h^3 Re<psi_j^n|H psi_j^n> (that step's
+ * V) and is the one-step start from psi^n instead of the two-step update.
+ * W_jp is 0 (the evolution keeps the orbitals orthonormal up to the scheme's own
+ * error).  The nuclei are moved by the caller (lbks_set_nuclei between steps;
+ * lbks_forces gives the Hellmann-Feynman forces of the current density).
+ * Times in atomic units (1 fs = 41.341 a.u.).  FP64 contexts with a local
+ * functional, omega = 1 and Gram-Schmidt only; not for batch members.  While
+ * the dynamics runs, lbks_relax, lbks_energy, lbks_hamiltonian, lbks_orbitals
+ * and lbks_set_orbitals return LBKS_E_STATE. */
+
+/* Start from the current orbitals (orthonormalised; normally a relaxed ground
+ * state): psi^0 = psi_hat, V_H converged for its density, E_j = eps_j of that
+ * state, and psi^1 = psi^0 - i h H' psi^0 - (h^2 / 2) H' H' psi^0, H' = H - E_j.  Allocates the complex
+ * orbitals (4 n_orb sites double2: two time levels and two work levels) through
+ * the context's allocator on the first start.  LBKS_E_INVAL for a context that
+ * is not FP64, local-functional, omega = 1, Gram-Schmidt, or for h outside
+ * (0, 0.95 / bound) with bound = max((1 - min symbol of S_xi) / (D dx^2), depth
+ * of V_ext at the nodes nearest the nuclei), or restart_every < 0;
+ * LBKS_E_STATE without a potential or for a batch member; LBKS_E_NOMEM.
+ * restart_every: steps restart_every, 2 restart_every, ... (counted from this
+ * start) are restarts; 0 = never (a few hundred steps suit moving nuclei). */
+int lbks_cd_start(lbks_ctx *ctx, double h, int64_t restart_every);
+
+/* Advance `steps` time steps with the current nuclei.  A restart step reads the
+ * orbital energies back to the host (one synchronisation). */
+int lbks_cd_step(lbks_ctx *ctx, int64_t steps);
+
+/* Energies of psi^n (host struct): the terms of lbks_energy with
+ * Re <psi_j|K_h psi_j> and Re <psi_j|S_chi(V psi_j)> (eps_j is the latter's sum),
+ * after converging V_H for the current density (kept); steps = time steps since
+ * the start.  LBKS_E_NUMERIC if a value is not finite (an unstable step). */
+int lbks_cd_energy(lbks_ctx *ctx, lbks_energies *out);
+
+/* Copy psi^n: real and imaginary parts (host, FP64, [n_orb][z][y][x] each,
+ * n >= n_orb * sites). */
+int lbks_cd_orbitals(lbks_ctx *ctx, double *re, double *im, size_t n);
+
+/* Leave the dynamics and free the complex orbitals; the relaxation state
+ * (populations) is the one from before lbks_cd_start. */
+int lbks_cd_stop(lbks_ctx *ctx);
 
 /* Replace V_ext by an arbitrary potential (host, FP64, one value per node);
  * the ion-ion energy becomes zero.  Used for model wells (harmonic

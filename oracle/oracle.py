@@ -126,6 +126,28 @@ def lattice(D: float = 1.0 / 3.0):
     return v, w, xi, chi
 
 
+def lattice4(D: float = 1.0 / 3.0):
+    """(v, w, xi, chi) with fourth-order Hermite weights on the D3Q19 velocities
+    (the paper's He run takes fourth order for the equilibrium and the source):
+    one value per speed class (rest, faces, edges) from the moment conditions
+      xi:  sum_p xi_p = 1,  sum_p xi_p v_x^2 = D,  sum_p xi_p v_x^2 v_y^2 = D^2
+           (zeroth, second and mixed fourth moments of a Gaussian of variance D),
+      chi: sum_p chi_p = 1, sum_p chi_p v_x^2 = 0, sum_p chi_p v_x^2 v_y^2 = 0,
+    solved as a 3 x 3 linear system (on D3Q19, v_x^4 = v_x^2, so these are all the
+    independent even moments up to fourth order)."""
+    v, w, _, _ = lattice(D)
+    cls = (v.astype(np.int64) ** 2).sum(1)
+    A = np.zeros((3, 3))
+    for c in range(3):
+        sel = cls == c
+        A[0, c] = sel.sum()
+        A[1, c] = float((v[sel, 0] ** 2).sum())
+        A[2, c] = float((v[sel, 0] ** 2 * v[sel, 1] ** 2).sum())
+    xc = np.linalg.solve(A, np.array([1.0, D, D * D]))
+    cc = np.linalg.solve(A, np.array([1.0, 0.0, 0.0]))
+    return v, w, np.ascontiguousarray(xc[cls]), np.ascontiguousarray(cc[cls])
+
+
 def occupations(n_elec: int, n_orb: int, polarised: bool = False) -> np.ndarray:
     """Closed-shell reading: 2 electrons per orbital, the last takes the rest.  A
     fully spin-polarised density has one electron in each orbital."""
@@ -197,6 +219,7 @@ class Params:
     occ: Optional[np.ndarray] = None
     deps_tol: float = 0.0           # stopping rule: > 0 also bounds the change of sum_j eps_j
     stop_checks: int = 0            # consecutive passing checks needed (0, 1: one)
+    hermite: int = 2                # order of the Hermite weights: 2, or 4 (lattice4)
 
     @property
     def dt(self) -> float:
@@ -231,7 +254,7 @@ class Oracle:
         self.L = lib()
         nx, ny, nz = prm.dims
         self.N = prm.n_sites
-        self.v, self.w, self.xi, self.chi = lattice(prm.D)
+        self.v, self.w, self.xi, self.chi = lattice4(prm.D) if prm.hermite == 4 else lattice(prm.D)
         self.occ = (np.asarray(prm.occ, dtype=np.float64) if prm.occ is not None
                     else occupations(prm.n_elec, prm.n_orb, prm.xc == XC_B88_LYP_POLARISED))
         self.f = np.zeros((prm.n_orb, Q, self.N))
@@ -342,10 +365,17 @@ class Oracle:
             V += vc
         return V, (ex, ec, vx, vc)
 
-    def step(self):
+    def step(self, active=None):
+        """One lattice step.  `active` (a set of orbital indices, None: all): the
+        orbitals outside it keep their populations (the sequential order of the
+        Gram-Schmidt procedure, relax_sequential); every orbital still enters the
+        orthonormalisation and the density."""
         if self.vext is None:
             raise RuntimeError("no potential set")
         p = self.prm
+        keep = None
+        if active is not None:
+            keep = {j: self.f[j].copy() for j in range(p.n_orb) if j not in active}
         if self.fields is not None:
             # leave the field form: the populations at equilibrium with the fields
             # (at omega = 1 the step below does not read them beyond their moment)
@@ -362,6 +392,9 @@ class Oracle:
                            _p(psistar), _p(psihat), _p(V), _p(self.fpost))
         nx, ny, nz = p.dims
         self.L.orc_stream(p.n_orb, nx, ny, nz, _p(self.v), _p(self.fpost), _p(self.f))
+        if keep:
+            for j, fj in keep.items():
+                self.f[j] = fj
         self.steps += 1
 
     def step_fields(self):
@@ -534,6 +567,43 @@ class Oracle:
         return 1, done
 
 
+def relax_sequential(o: "Oracle", max_steps: int, dE_tol: float, deps_tol: float, check_every: int = 50,
+                     max_sweeps: int = 20, progress=None):
+    """The sequential order of the time-dependent Gram-Schmidt procedure (the
+    closing remark on eq. KSLB-2: evolve psi_0 to its ground state, then psi_1, and
+    so on), in this reading: in stage k only orbital k takes lattice steps (the
+    others keep their populations), every orbital is orthonormalised in order each
+    step (so orbital k is projected against the converged lower ones) and the
+    density is that of all orbitals in their current state; stage k ends when eps_k
+    changed by less than deps_tol over check_every steps.  A sweep runs the stages
+    k = 0 .. n-1; sweeps repeat until the total energy changed by less than dE_tol
+    from the previous sweep (the density of the later orbitals drives V in the
+    earlier stages, so one sweep is not self-consistent).  Returns
+    (0 converged | 1 step limit, steps, sweeps)."""
+    n = o.prm.n_orb
+    steps, e_prev = 0, None
+    for sweep in range(1, max_sweeps + 1):
+        for k in range(n):
+            eps_prev = None
+            while steps < max_steps:
+                for _ in range(check_every):
+                    o.step(active={k})
+                steps += check_every
+                eps = o.energies(converge_poisson=False).eps[k]
+                if progress is not None:
+                    progress(sweep, k, steps, eps)
+                if eps_prev is not None and abs(eps - eps_prev) < deps_tol:
+                    break
+                eps_prev = eps
+        e = o.energies(converge_poisson=False).e_total
+        if steps >= max_steps:
+            return 1, steps, sweep
+        if e_prev is not None and abs(e - e_prev) < dE_tol:
+            return 0, steps, sweep
+        e_prev = e
+    return 1, steps, max_sweeps
+
+
 def params_for(system, **kw) -> Params:
     """Oracle parameters for an inputs.System."""
     return Params(dims=tuple(system.dims), h=system.h, n_orb=system.n_orb, n_elec=system.n_elec,
@@ -555,19 +625,31 @@ class ConcurrentDynamics:
         f_jp = xi_p psi_j (the omega = 1 reading of the relaxation, where the
         populations carry nothing beyond their moment), so the two-step
         time-centred lattice equation advances the moments:
-            psi_j^{n+1} = psi_j^{n-1} - 2 i h H psi_j^n,
+            psi_j^{n+1} = psi_j^{n-1} - 2 i h (H - E_j) psi_j^n,
             H u = K_h u + S_chi(V u),  K_h u = -(S_xi u - u) / (D dx^2),
         H being the operator whose steady state the relaxation reaches (its
         Rayleigh quotients are the eps_j), with the potential and orthogonality
         sources turned by i as printed;
-      * U_jp = kappa w_p q_p E_j phi_j has no zeroth or first moment, so with the
-        populations at equilibrium it leaves the orbitals unchanged: kappa = 0,
-        and the energy is kept by the time-centred scheme itself;
+      * U_jp = kappa w_p q_p E_j phi_j, "in charge of keeping the energy at E_j",
+        is read as each orbital's energy reference: orbital j is advanced with
+        H - E_j, E_j its Rayleigh quotient at the start.  That is a global phase
+        e^{i E_j t} per orbital (densities, energies and forces are unchanged) which
+        makes the ground state stationary; without it the density picks up the
+        two-step scheme's parasitic (-1)^n mode and, fed back through V, it grows
+        exponentially (measured on H2 at 0.45 bohr and 0.0014 fs: tenfold every
+        500 steps from step 1500 on);
+      * the energy reference alone does not hold once the nuclei move: the
+        orbitals' energies drift away from E_j and the parasitic mode grows again
+        (measured on the same H2 vibrating: the total energy departs by 2e-3
+        hartree after 6000 steps).  With restart_every = R > 0, every R-th step
+        (steps R, 2R, ... counted from the start) is a restart: E_j is re-centred
+        on h^3 Re<psi_j^n|H psi_j^n> with that step's V, and the step is the
+        one-step start below taken from psi^n, which leaves no parasitic mode;
       * W = 0: the evolution is unitary up to the scheme's own error, which keeps
         the orbitals orthonormal (the drift is measured, not corrected);
       * start: psi^0 = the orthonormalised current orbitals (a relaxed ground
-        state), V_H converged for their density, and
-        psi^1 = psi^0 - i h H psi^0 - (h^2/2) H H psi^0;
+        state), V_H converged for their density, E_j = <psi_j^0|H psi_j^0>, and
+        psi^1 = psi^0 - i h H' psi^0 - (h^2/2) H' H' psi^0, H' = H - E_j;
       * each step first rebuilds V from rho^n = sum_j occ_j |psi_j^n|^2 (multipole
         boundary and K_P warm-started red/black sweeps, as in the relaxation),
         then takes the step above;
@@ -575,9 +657,12 @@ class ConcurrentDynamics:
         Hellmann-Feynman forces of the instantaneous density.
     h is the time step in atomic units of real time.  Test infrastructure only."""
 
-    def __init__(self, o: "Oracle", h: float):
+    def __init__(self, o: "Oracle", h: float, eref=None, restart_every: int = 0):
+        """eref: the energy references E_j (default: the orbitals' Rayleigh
+        quotients at the start); restart_every: period of the restarts (0: none)."""
         self.o = o
         self.h = float(h)
+        self.restart_every = int(restart_every)
         p = o.prm
         if p.omega != 1.0 or p.ortho != "gs":
             raise ValueError("concurrent dynamics starts from the omega = 1 Gram-Schmidt relaxation")
@@ -587,6 +672,9 @@ class ConcurrentDynamics:
         if p.hartree:
             o.converge_poisson(rho)
         V, _ = o.potential(rho)
+        if eref is None:
+            eref = self.rayleigh(self.prev, V)
+        self.eref = np.asarray(eref, dtype=np.float64).reshape(p.n_orb)
         h1 = self.apply_h(self.prev, V)
         h2 = self.apply_h(h1, V)
         self.cur = self.prev - 1j * self.h * h1 - 0.5 * self.h * self.h * h2
@@ -598,15 +686,19 @@ class ConcurrentDynamics:
         im = np.ascontiguousarray(psi.imag)
         return self.o.density(re) + self.o.density(im)
 
-    def apply_h(self, psi, V):
-        """H psi for complex psi [n][N], on the real and imaginary parts."""
+    def apply_h(self, psi, V, shift=True):
+        """(H - E_j) psi_j for complex psi [n][N] (H psi with shift=False), on the
+        real and imaginary parts."""
         p = self.o.prm
         out = np.empty_like(psi)
         for j in range(psi.shape[0]):
             parts = []
             for u in (np.ascontiguousarray(psi[j].real), np.ascontiguousarray(psi[j].imag)):
                 su = apply_sw(p.dims, self.o.v, self.o.xi, u)
-                parts.append(-(su - u) / (p.D * p.h * p.h) + apply_sw(p.dims, self.o.v, self.o.chi, V * u))
+                hu = -(su - u) / (p.D * p.h * p.h) + apply_sw(p.dims, self.o.v, self.o.chi, V * u)
+                if shift:
+                    hu = hu - self.eref[j] * u
+                parts.append(hu)
             out[j] = parts[0] + 1j * parts[1]
         return out
 
@@ -620,9 +712,20 @@ class ConcurrentDynamics:
         V, _ = self.o.potential(rho)
         return V
 
+    def rayleigh(self, psi, V):
+        """h^3 Re<psi_j|H psi_j> per orbital."""
+        hp = self.apply_h(psi, V, shift=False)
+        return np.array([self.o.prm.h ** 3 * np.vdot(psi[j], hp[j]).real for j in range(psi.shape[0])])
+
     def step(self):
         V = self.potential_now()
-        new = self.prev - 2j * self.h * self.apply_h(self.cur, V)
+        if self.restart_every > 0 and (self.steps + 1) % self.restart_every == 0:
+            self.eref = self.rayleigh(self.cur, V)
+            h1 = self.apply_h(self.cur, V)
+            h2 = self.apply_h(h1, V)
+            new = self.cur - 1j * self.h * h1 - 0.5 * self.h * self.h * h2
+        else:
+            new = self.prev - 2j * self.h * self.apply_h(self.cur, V)
         self.prev, self.cur = self.cur, new
         self.steps += 1
 

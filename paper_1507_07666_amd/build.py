@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbks.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["lbks_kernels.hip", "lbks_collide.hip", "lbks_capi.hip"]
+SOURCES = ["lbks_kernels.hip", "lbks_collide.hip", "lbks_cd.hip", "lbks_capi.hip"]
 ARCH = os.environ.get("LBKS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -62,6 +62,17 @@ struct lbks_ctx {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     lbks_batch *batch = nullptr;
+    // concurrent dynamics (lbks_cd_*): complex orbitals at two time levels plus two
+    // work levels, [4][n_orb][site] of double2
+    bool cd = false;
+    double cd_h = 0.0;
+    double2 *cd_buf = nullptr;
+    int cd_cur = 1;             // level holding psi^n (the other of levels 0, 1 holds psi^{n-1})
+    int64_t cd_steps = 0;
+    CdRef cd_ref{};             // energy reference E_j of each orbital (its energy at the last (re)start)
+    int64_t cd_restart = 0;     // period of the restarts (0: none)
+    std::vector<double> nuc;    // nuclei of the last lbks_set_nuclei: Z, x, y, z per nucleus
+    double vext_depth = 0.0;    // max |v| of a potential from lbks_set_potential
 };
 
 // One launch group of a batch: members sharing every template and sequence choice.
@@ -126,14 +137,22 @@ int hip_fail(lbks_ctx *c, hipError_t e, const char *where)
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// D3Q19 weights, equilibrium xi_p = w_p (1 + (D - c_s^2) q_p) and potential source
-// chi_p = w_p (1 - c_s^2 q_p), q_p = (|v_p|^2 - 3 c_s^2) / (2 c_s^4), c_s^2 = 1/3,
-// in the velocity order of the kernels (rest, 6 faces, 12 edges).
-void lattice_constants(double D, double *xi, double *chi)
+// D3Q19 weights in the velocity order of the kernels (rest, 6 faces, 12 edges).
+// Second order: equilibrium xi_p = w_p (1 + (D - c_s^2) q_p) and potential source
+// chi_p = w_p (1 - c_s^2 q_p), q_p = (|v_p|^2 - 3 c_s^2) / (2 c_s^4), c_s^2 = 1/3.
+// Fourth order: xi also matches the mixed fourth moment D^2 of a Gaussian of
+// variance D (rest 1 - 3D + 3D^2, faces D/2 - D^2, edges D^2/4), and chi has no
+// second or mixed fourth moment (all of it on the rest velocity).
+void lattice_constants(double D, int hermite, double *xi, double *chi)
 {
     const double cs2 = 1.0 / 3.0;
     for (int p = 0; p < Q; ++p) {
         const int v2 = p == 0 ? 0 : (p <= 6 ? 1 : 2);
+        if (hermite == 4) {
+            xi[p] = v2 == 0 ? 1.0 - 3.0 * D + 3.0 * D * D : (v2 == 1 ? 0.5 * D - D * D : 0.25 * D * D);
+            chi[p] = v2 == 0 ? 1.0 : 0.0;
+            continue;
+        }
         const double w = v2 == 0 ? 1.0 / 3.0 : (v2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
         const double q = ((double)v2 - 3.0 * cs2) / (2.0 * cs2 * cs2);
         xi[p] = w * (1.0 + (D - cs2) * q);
@@ -168,7 +187,13 @@ int validate(const lbks_params *p, std::string &why)
         return LBKS_E_INVAL;
     }
     if (!(p->omega > 0.0 && p->omega < 2.0)) { why = "omega must lie in (0, 2)"; return LBKS_E_INVAL; }
-    if (!(p->D > 0.0 && p->D <= 7.0 / 18.0 + 1e-15)) {
+    if (p->hermite != 0 && p->hermite != 2 && p->hermite != 4) { why = "hermite must be 0, 2 or 4"; return LBKS_E_INVAL; }
+    if (p->hermite == 4) {
+        if (!(p->D > 0.0 && p->D <= 0.5 + 1e-15)) {
+            why = "D must lie in (0, 1/2] with fourth-order weights: larger D makes the relaxation stencil's symbol negative";
+            return LBKS_E_INVAL;
+        }
+    } else if (!(p->D > 0.0 && p->D <= 7.0 / 18.0 + 1e-15)) {
         why = "D must lie in (0, 7/18]: larger D makes the relaxation stencil's symbol negative";
         return LBKS_E_INVAL;
     }
@@ -186,7 +211,7 @@ int validate(const lbks_params *p, std::string &why)
     }
     if (p->stop_checks < 0 || p->stop_checks > 1000) { why = "stop_checks must be in [0, 1000]"; return LBKS_E_INVAL; }
     if (!(p->deps_tol >= 0.0) || !isfinite(p->deps_tol)) { why = "deps_tol must be finite and >= 0"; return LBKS_E_INVAL; }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i]) { why = "reserved fields must be zero"; return LBKS_E_INVAL; }
     return 0;
 }
@@ -541,6 +566,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
         h.omega_sor = 2.0 / (1.0 + sqrt(1.0 - mu * mu));
     }
     h.rho_floor = p->rho_floor;
+    h.active = ~0u;
     h.e_nn = 0.0;
     for (int j = 0; j < MAXO; ++j) h.occ[j] = 0.0;
     if (p->xc == LBKS_XC_B88_LYP_POLARISED) {
@@ -549,7 +575,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
         for (int j = 0; j < p->n_orb; ++j) h.occ[j] = 2.0;
         h.occ[p->n_orb - 1] = (double)p->n_elec - 2.0 * (p->n_orb - 1);
     }
-    lattice_constants(p->D, h.xi, h.chi);
+    lattice_constants(p->D, p->hermite, h.xi, h.chi);
     h.f0 = at(L.f0);
     h.f1 = at(L.f1);
     h.psi = at(L.psi);
@@ -632,6 +658,7 @@ extern "C" void lbks_destroy(lbks_ctx *c)
     if (c->batch) lbks_batch_detach(c->batch, c);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    dev_free(c, c->cd_buf);
     dev_free(c, c->base);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -683,6 +710,7 @@ extern "C" int lbks_set_nuclei(lbks_ctx *c, int32_t n, const double *Z, const do
         }
     HIPCHK(c, hipMemcpyAsync(c->d_zr, zr, sizeof(double) * (4 * n + 1), hipMemcpyHostToDevice, c->stream));
     KCHK(c, launch_vext(c->plan, n, c->d_zr, c->stream));
+    c->nuc.assign(zr, zr + 4 * n);
     c->h.e_nn = enn;
     c->h.nnuc = n;
     int rc = upload_desc(c);
@@ -697,6 +725,9 @@ extern "C" int lbks_set_potential(lbks_ctx *c, const double *v)
     HIPCHK(c, hipMemcpyAsync(c->h.vext, v, sizeof(double) * (size_t)c->h.nsite, hipMemcpyHostToDevice, c->stream));
     c->h.e_nn = 0.0;
     c->h.nnuc = 0;
+    c->nuc.clear();
+    c->vext_depth = 0.0;
+    for (int i = 0; i < c->h.nsite; ++i) c->vext_depth = std::max(c->vext_depth, fabs(v[i]));
     int rc = upload_desc(c);
     if (rc) return rc;
     c->has_potential = true;
@@ -705,6 +736,7 @@ extern "C" int lbks_set_potential(lbks_ctx *c, const double *v)
 
 extern "C" int lbks_set_orbitals(lbks_ctx *c, const double *psi)
 {
+    if (c && c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
     if (!c || !psi) return LBKS_E_INVAL;
     const size_t n = (size_t)c->p.n_orb * c->h.nsite;
     reset_rule(c);
@@ -733,6 +765,7 @@ extern "C" int lbks_set_orbitals(lbks_ctx *c, const double *psi)
 extern "C" int lbks_relax(lbks_ctx *c, int64_t max_steps, double dE_tol, int32_t check_every, int64_t *steps_done)
 {
     if (!c) return LBKS_E_INVAL;
+    if (c && c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
     if (steps_done) *steps_done = 0;
     if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     if (max_steps < 0) return fail(c, LBKS_E_INVAL, "max_steps < 0");
@@ -766,11 +799,21 @@ namespace {
 
 // Orthonormalise the current orbitals and, with Hartree on, converge V_H for
 // their density (the state lbks_energy and lbks_hamiltonian evaluate).
+int converge_vh(lbks_ctx *c);
+
 int converge_hartree(lbks_ctx *c)
 {
     int rc;
     reset_rule(c);   // the Hartree relaxation below changes the state
     if ((rc = enqueue_orthonormalise(c))) return rc;
+    return converge_vh(c);
+}
+
+// Converge V_H for the density in place (multipole partials of that density in
+// m_part).
+int converge_vh(lbks_ctx *c)
+{
+    int rc;
     if (c->p.hartree) {
         if ((rc = enqueue_hartree_boundary(c))) return rc;
         // converge V_H for the current density: blocks of 10 sweeps until the
@@ -804,6 +847,7 @@ int converge_hartree(lbks_ctx *c)
 extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
 {
     if (!c || !out) return LBKS_E_INVAL;
+    if (c && c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
     if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     int rc;
     if ((rc = converge_hartree(c))) return rc;
@@ -818,6 +862,7 @@ extern "C" int lbks_energy(lbks_ctx *c, lbks_energies *out)
 extern "C" int lbks_hamiltonian(lbks_ctx *c, double *H, size_t n_H)
 {
     if (!c || !H) return LBKS_E_INVAL;
+    if (c && c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
     if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
     const size_t n = (size_t)c->p.n_orb;
     if (n_H < n * n) return fail(c, LBKS_E_INVAL, "H buffer too small");
@@ -844,6 +889,285 @@ extern "C" int lbks_hamiltonian(lbks_ctx *c, double *H, size_t n_H)
     return 0;
 }
 
+extern "C" int lbks_relax_sequential(lbks_ctx *c, int64_t max_steps, double dE_tol, double deps_tol,
+                                     int32_t check_every, int32_t max_sweeps, int64_t *steps_done,
+                                     int32_t *sweeps_done)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (steps_done) *steps_done = 0;
+    if (sweeps_done) *sweeps_done = 0;
+    if (c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    if (c->batch) return fail(c, LBKS_E_STATE, "a batch member relaxes with the batch");
+    if (c->p.scheme != LBKS_SCHEME_COLLAPSED || c->p.ortho != LBKS_ORTHO_GS)
+        return fail(c, LBKS_E_INVAL, "the sequential order runs on the omega = 1 field update with Gram-Schmidt");
+    if (!(dE_tol > 0.0) || !(deps_tol > 0.0) || max_steps < 0 || max_sweeps < 1)
+        return fail(c, LBKS_E_INVAL, "dE_tol and deps_tol must be positive, max_sweeps >= 1");
+    if (check_every < 1) check_every = 1;
+    const int n = c->p.n_orb;
+    int64_t steps = 0;
+    int rc = LBKS_NOT_CONVERGED, sweep = 0;
+    double e_prev = 0.0;
+    bool have_prev = false;
+    auto set_active = [&](unsigned mask) -> int {
+        c->h.active = mask;
+        return upload_desc(c);
+    };
+    auto energies = [&](lbks_energies *e) -> int {
+        int r;
+        if ((r = enqueue_energy(c))) return r;
+        double errf = 0.0;
+        if ((r = read_energies(c, e, &errf))) return r;
+        if (errf != 0.0 || !isfinite(e->e_total))
+            return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+        return 0;
+    };
+    int err = 0;
+    for (sweep = 1; sweep <= max_sweeps && !err; ++sweep) {
+        for (int k = 0; k < n && !err; ++k) {
+            if ((err = set_active(1u << k))) break;
+            bool have = false;
+            double eps_prev = 0.0;
+            while (steps < max_steps) {
+                const int64_t m = std::min<int64_t>(check_every, max_steps - steps);
+                for (int64_t i = 0; i < m && !err; ++i) err = enqueue_step(c);
+                if (err) break;
+                steps += m;
+                lbks_energies e;
+                if ((err = energies(&e))) break;
+                if (have && fabs(e.eps[k] - eps_prev) < deps_tol) break;
+                eps_prev = e.eps[k];
+                have = true;
+            }
+        }
+        if (err) break;
+        lbks_energies e;
+        if ((err = energies(&e))) break;
+        if (steps >= max_steps) break;
+        if (have_prev && fabs(e.e_total - e_prev) < dE_tol) {
+            rc = LBKS_OK;
+            break;
+        }
+        e_prev = e.e_total;
+        have_prev = true;
+    }
+    const int e2 = set_active(~0u);
+    if (steps_done) *steps_done = steps;
+    if (sweeps_done) *sweeps_done = std::min(sweep, max_sweeps);
+    if (err) return err;
+    if (e2) return e2;
+    reset_rule(c);
+    return rc;
+}
+
+// ================================================ concurrent dynamics
+
+namespace {
+
+double2 *cd_level(lbks_ctx *c, int k) { return c->cd_buf + (size_t)k * c->p.n_orb * c->h.nsite; }
+
+// V of the density in place: multipole boundary, K_P red/black sweeps, potential.
+int cd_potential(lbks_ctx *c)
+{
+    const Plan &pl = c->plan;
+    if (c->p.hartree) {
+        KCHK(c, launch_multipole_finalize(pl, c->stream));
+        KCHK(c, launch_ghost(pl, c->stream));
+        const int sw = c->p.poisson_sweeps;
+        for (int k = 0; k < sw; ++k) {
+            KCHK(c, launch_sor(pl, 0, c->stream));
+            if (k + 1 < sw) KCHK(c, launch_sor(pl, 1, c->stream));
+        }
+        if (sw > 0) {
+            KCHK(c, launch_sor_black_potential(pl, c->stream));
+            return 0;
+        }
+    }
+    KCHK(c, launch_potential(pl, 0, c->stream));
+    return 0;
+}
+
+// Bound of the kinetic part of H for the stability of the time-centred step:
+// (1 - min symbol of S_xi) / (D dx^2) over a grid of wave vectors.
+void cd_bounds(const lbks_ctx *c, double *kin, double *vdepth)
+{
+    double smin = 1.0;
+    const int K = 16;
+    for (int a = 0; a <= K; ++a)
+        for (int b = 0; b <= K; ++b)
+            for (int e = 0; e <= K; ++e) {
+                const double kx = M_PI * a / K, ky = M_PI * b / K, kz = M_PI * e / K;
+                double sym = 0.0;
+                for (int p = 0; p < Q; ++p) {
+                    const int vx = (p == 1 || p == 7 || p == 9 || p == 11 || p == 13) ? 1
+                                 : (p == 2 || p == 8 || p == 10 || p == 12 || p == 14) ? -1 : 0;
+                    const int vy = (p == 3 || p == 7 || p == 8 || p == 15 || p == 17) ? 1
+                                 : (p == 4 || p == 9 || p == 10 || p == 16 || p == 18) ? -1 : 0;
+                    const int vz = (p == 5 || p == 11 || p == 12 || p == 15 || p == 16) ? 1
+                                 : (p == 6 || p == 13 || p == 14 || p == 17 || p == 18) ? -1 : 0;
+                    sym += c->h.xi[p] * cos(kx * vx + ky * vy + kz * vz);
+                }
+                smin = std::min(smin, sym);
+            }
+    *kin = (1.0 - smin) / (c->p.D * c->p.h * c->p.h);
+    *vdepth = 0.0;
+}
+
+}  // namespace
+
+extern "C" int lbks_cd_start(lbks_ctx *c, double h, int64_t restart_every)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (restart_every < 0) return fail(c, LBKS_E_INVAL, "restart_every < 0");
+    if (!c->has_potential) return fail(c, LBKS_E_STATE, "no nuclei or potential set");
+    if (c->batch) return fail(c, LBKS_E_STATE, "a batch member cannot run concurrent dynamics (detach it)");
+    if (c->p.precision != LBKS_FP64 || c->p.xc >= LBKS_XC_B88_LYP || c->p.omega != 1.0 ||
+        c->p.ortho != LBKS_ORTHO_GS)
+        return fail(c, LBKS_E_INVAL, "concurrent dynamics needs FP64, a local functional, omega = 1 and Gram-Schmidt");
+    if (!(h > 0.0) || !isfinite(h)) return fail(c, LBKS_E_INVAL, "time step must be positive");
+    double kin = 0.0, vdepth = 0.0;
+    cd_bounds(c, &kin, &vdepth);
+    // depth of V_ext at the node nearest each nucleus (what the grid resolves), or
+    // the largest |v| of a potential set directly
+    if (c->nuc.empty()) vdepth = c->vext_depth;
+    for (size_t I = 0; 4 * I + 3 < c->nuc.size(); ++I) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double half = 0.5 * (c->p.N[a] - 1) * c->p.h;
+            const double t = (c->nuc[4 * I + 1 + a] + half) / c->p.h;
+            const double dn = (t - floor(t + 0.5)) * c->p.h;
+            d2 += dn * dn;
+        }
+        vdepth += c->nuc[4 * I] / sqrt(d2 + c->p.softening * c->p.softening);
+    }
+    const double lam = std::max(kin, vdepth);
+    if (h * lam >= 0.95) {
+        char msg[200];
+        snprintf(msg, sizeof msg, "time step %.4g exceeds the stable bound 0.95 / %.4g = %.4g of the time-centred step", h,
+                 lam, 0.95 / lam);
+        return fail(c, LBKS_E_INVAL, msg);
+    }
+    const size_t lvl = (size_t)c->p.n_orb * c->h.nsite;
+    if (!c->cd_buf) {
+        c->cd_buf = (double2 *)dev_alloc(c, 4 * lvl * sizeof(double2));
+        if (!c->cd_buf) return fail(c, LBKS_E_NOMEM, "device allocation of the complex orbitals failed");
+    }
+    int rc;
+    c->cd = false;
+    if ((rc = converge_hartree(c))) return rc;     // psi_hat, rho and V_H of the current orbitals
+    // energy references: the orbitals' energies eps_j at the start
+    if ((rc = enqueue_energy(c))) return rc;
+    {
+        lbks_energies e0;
+        double errf = 0.0;
+        if ((rc = read_energies(c, &e0, &errf))) return rc;
+        if (errf != 0.0) return fail(c, LBKS_E_NUMERIC, "overlap matrix not finite or not positive definite");
+        for (int j = 0; j < MAXO; ++j) c->cd_ref.e[j] = j < c->p.n_orb ? e0.eps[j] : 0.0;
+    }
+    KCHK(c, launch_potential(c->plan, 0, c->stream));
+    KCHK(c, launch_cd_init(c->plan, cd_level(c, 0), c->stream));
+    KCHK(c, launch_cd_apply(c->plan, cd_level(c, 0), cd_level(c, 2), c->cd_ref, c->stream));
+    KCHK(c, launch_cd_apply(c->plan, cd_level(c, 2), cd_level(c, 3), c->cd_ref, c->stream));
+    KCHK(c, launch_cd_taylor(c->plan, cd_level(c, 0), cd_level(c, 2), cd_level(c, 3), cd_level(c, 1), h, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cd = true;
+    c->cd_h = h;
+    c->cd_cur = 1;
+    c->cd_steps = 0;
+    c->cd_restart = restart_every;
+    return 0;
+}
+
+namespace {
+
+// Restart step (V of psi^n in place): E_j <- h^3 Re<psi_j^n|H psi_j^n>, then the
+// new level is the one-step start from psi^n, psi^n - i h H' psi^n - (h^2 / 2) H' H' psi^n.
+int cd_restart_step(lbks_ctx *c)
+{
+    const Plan &pl = c->plan;
+    double2 *cur = cd_level(c, c->cd_cur);
+    KCHK(c, launch_cd_energy_terms(pl, cur, c->stream));
+    KCHK(c, launch_energy_finalize(pl, c->stream));
+    lbks_energies e;
+    int rc;
+    if ((rc = read_energies(c, &e, nullptr))) return rc;
+    for (int j = 0; j < c->p.n_orb; ++j)
+        if (!isfinite(e.eps[j])) return fail(c, LBKS_E_NUMERIC, "orbital energy not finite at a restart");
+    for (int j = 0; j < MAXO; ++j) c->cd_ref.e[j] = j < c->p.n_orb ? e.eps[j] : 0.0;
+    KCHK(c, launch_cd_apply(pl, cur, cd_level(c, 2), c->cd_ref, c->stream));
+    KCHK(c, launch_cd_apply(pl, cd_level(c, 2), cd_level(c, 3), c->cd_ref, c->stream));
+    KCHK(c, launch_cd_taylor(pl, cur, cd_level(c, 2), cd_level(c, 3), cd_level(c, 1 - c->cd_cur), c->cd_h,
+                             c->stream));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int lbks_cd_step(lbks_ctx *c, int64_t steps)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (!c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics not started (lbks_cd_start)");
+    if (steps < 0) return fail(c, LBKS_E_INVAL, "steps < 0");
+    int rc;
+    for (int64_t k = 0; k < steps; ++k) {
+        if ((rc = cd_potential(c))) return rc;
+        if (c->cd_restart > 0 && (c->cd_steps + 1) % c->cd_restart == 0) {
+            if ((rc = cd_restart_step(c))) return rc;
+        } else {
+            KCHK(c, launch_cd_step(c->plan, cd_level(c, c->cd_cur), cd_level(c, 1 - c->cd_cur), c->cd_h, c->cd_ref,
+                                   c->stream));
+        }
+        c->cd_cur = 1 - c->cd_cur;
+        c->cd_steps += 1;
+    }
+    return 0;
+}
+
+extern "C" int lbks_cd_energy(lbks_ctx *c, lbks_energies *out)
+{
+    if (!c || !out) return LBKS_E_INVAL;
+    if (!c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics not started (lbks_cd_start)");
+    int rc;
+    if ((rc = converge_vh(c))) return rc;
+    KCHK(c, launch_potential(c->plan, 1, c->stream));
+    KCHK(c, launch_cd_energy_terms(c->plan, cd_level(c, c->cd_cur), c->stream));
+    KCHK(c, launch_energy_finalize(c->plan, c->stream));
+    if ((rc = read_energies(c, out, nullptr))) return rc;
+    if (!c->p.hartree) out->poisson_residual = 0.0;
+    out->steps = c->cd_steps;
+    for (int j = 0; j < LBKS_MAX_ORB; ++j)
+        if (!isfinite(out->eps[j])) return fail(c, LBKS_E_NUMERIC, "orbital energy not finite");
+    if (!isfinite(out->e_total)) return fail(c, LBKS_E_NUMERIC, "total energy not finite");
+    return 0;
+}
+
+extern "C" int lbks_cd_orbitals(lbks_ctx *c, double *re, double *im, size_t n)
+{
+    if (!c || !re || !im) return LBKS_E_INVAL;
+    if (!c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics not started (lbks_cd_start)");
+    const size_t lvl = (size_t)c->p.n_orb * c->h.nsite;
+    if (n < lvl) return fail(c, LBKS_E_INVAL, "orbital buffers too small");
+    std::vector<double2> host(lvl);
+    HIPCHK(c, hipMemcpyAsync(host.data(), cd_level(c, c->cd_cur), lvl * sizeof(double2), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < lvl; ++i) {
+        re[i] = host[i].x;
+        im[i] = host[i].y;
+    }
+    return 0;
+}
+
+extern "C" int lbks_cd_stop(lbks_ctx *c)
+{
+    if (!c) return LBKS_E_INVAL;
+    if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+    dev_free(c, c->cd_buf);
+    c->cd_buf = nullptr;
+    c->cd = false;
+    return 0;
+}
+
 static_assert(MAXNUC == LBKS_MAX_NUC, "nuclei capacity of the kernels and of the C ABI differ");
 
 extern "C" int lbks_forces(lbks_ctx *c, double *F, size_t n_F)
@@ -853,7 +1177,8 @@ extern "C" int lbks_forces(lbks_ctx *c, double *F, size_t n_F)
     if (nn < 1) return fail(c, LBKS_E_STATE, "no nuclei set (forces need lbks_set_nuclei)");
     if (n_F < (size_t)(3 * nn)) return fail(c, LBKS_E_INVAL, "force buffer too small");
     int rc;
-    if ((rc = enqueue_orthonormalise(c))) return rc;
+    // during concurrent dynamics the density of the current complex orbitals is in place
+    if (!c->cd && (rc = enqueue_orthonormalise(c))) return rc;
     for (int i0 = 0; i0 < nn; i0 += NUCG) {
         KCHK(c, launch_force_terms(c->plan, i0, c->stream));
         KCHK(c, launch_force_finalize(c->plan, i0, c->stream));
@@ -873,6 +1198,7 @@ extern "C" int lbks_forces(lbks_ctx *c, double *F, size_t n_F)
 extern "C" int lbks_orbitals(lbks_ctx *c, double *psi, size_t n_psi, double *rho, size_t n_rho)
 {
     if (!c || !psi) return LBKS_E_INVAL;
+    if (c && c->cd) return fail(c, LBKS_E_STATE, "concurrent dynamics is running (lbks_cd_stop first)");
     const size_t N = (size_t)c->h.nsite, n = (size_t)c->p.n_orb;
     if (n_psi < n * N) return fail(c, LBKS_E_INVAL, "psi buffer too small");
     if (rho && n_rho < N) return fail(c, LBKS_E_INVAL, "rho buffer too small");

@@ -290,6 +290,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
             }
         }
         T *psi = (T *)d.psi;
+        if (d.active != ~0u) {                      // sequential order: frozen orbitals keep their fields
+#pragma unroll
+            for (int j = 0; j < NO; ++j)
+                if (j < n && !((d.active >> j) & 1u)) acc[j] = psi[(size_t)j * N + s];
+        }
 #pragma unroll
         for (int j = 0; j < NO; ++j)
             if (j < n) psi[(size_t)j * N + s] = acc[j];
@@ -395,6 +400,11 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
                 for (int j = 0; j < NO; ++j) acc[j] += (cxi[c] - dp) * lds[j][slot][li];
             }
             const size_t s = ((size_t)z * ny + y) * nx + x;
+            if (d.active != ~0u) {                  // sequential order: frozen orbitals keep their fields
+#pragma unroll
+                for (int j = 0; j < NO; ++j)
+                    if (!((d.active >> j) & 1u)) acc[j] = psi[(size_t)j * N + s];
+            }
 #pragma unroll
             for (int j = 0; j < NO; ++j) psi[(size_t)j * N + s] = acc[j];
             int q = 0;

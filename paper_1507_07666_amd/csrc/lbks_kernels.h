@@ -60,6 +60,8 @@ struct InstDesc {
     int ortho, xc, hartree, precision;
     int scheme;
     int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
+    unsigned active;           // orbitals that take the omega = 1 field update (bit j); the others keep
+                               // their fields (the sequential Gram-Schmidt order); all ones otherwise
     double h, h3, omega, dt, D, omega_sor, rho_floor, e_nn;
     double occ[MAXO];
     double xi[Q], chi[Q];
@@ -157,6 +159,17 @@ int launch_gga(const Plan &pl, hipStream_t st);
 int launch_force_terms(const Plan &pl, int i0, hipStream_t st);     // nuclei i0 .. i0 + NUCG - 1
 int launch_force_finalize(const Plan &pl, int i0, hipStream_t st);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t st);
+// concurrent dynamics (complex FP64 orbitals [orbital][site] of double2, single instance);
+// orbital j is advanced with H - eref[j]
+struct CdRef {
+    double e[MAXO];
+};
+int launch_cd_init(const Plan &pl, double2 *prev, hipStream_t st);
+int launch_cd_apply(const Plan &pl, const double2 *in, double2 *out, const CdRef &ref, hipStream_t st);
+int launch_cd_taylor(const Plan &pl, const double2 *prev, const double2 *t1, const double2 *t2, double2 *cur,
+                     double h, hipStream_t st);
+int launch_cd_step(const Plan &pl, const double2 *cur, double2 *prev, double h, const CdRef &ref, hipStream_t st);
+int launch_cd_energy_terms(const Plan &pl, const double2 *cur, hipStream_t st);
 // dst[i * width + k] = scal_i[SC_ENER + k] (k < 25), dst[i * width + 25] = scal_i[SC_ERR]
 int launch_gather(const double *const *scal, int count, int width, double *dst, hipStream_t st);
 

@@ -15,7 +15,9 @@ module only moves the nuclei.
     from a rough start (the paper relaxes water from random hydrogen
     positions);
   * bo_md: velocity-Verlet molecular dynamics on the ground-state surface (the
-    paper's H2 vibration).
+    paper's H2 vibration);
+  * cd_md: the concurrent scenario, electrons (complex orbitals in real time)
+    and nuclei advanced together with one small time step.
 
 Units are atomic: bohr, hartree, electron masses, and atomic time
 (1 fs = 41.341 a.u.).
@@ -158,3 +160,79 @@ def bo_md(solver: lbks.Solver, Z: Sequence[float], R0, V0, masses: Sequence[floa
         ek.append(0.5 * float(np.sum(M * V * V)))
         ls.append(gs.steps)
     return Trajectory(np.array(ts), np.array(Rs), np.array(Vs), np.array(ep), np.array(ek), np.array(ls))
+
+
+@dataclass
+class CDTrajectory:
+    t: np.ndarray            # [n+1] atomic time
+    R: np.ndarray            # [n+1][nuclei][3]
+    V: np.ndarray            # [n+1][nuclei][3]
+    e_t: np.ndarray          # times of the energy records
+    e_pot: np.ndarray        # electronic + ion-ion energy at those times
+    e_kin: np.ndarray        # nuclear kinetic energy at those times
+
+
+def cd_md(solver: lbks.Solver, Z: Sequence[float], R0, V0, masses: Sequence[float], dt: float, n_steps: int,
+          energy_every: int = 0, fixed: Optional[Sequence[bool]] = None,
+          restart_every: int = 500) -> CDTrajectory:
+    """Concurrent dynamics (the paper's concurrent scenario, eq. KSLBCD): the
+    electrons, complex orbitals advanced by the library's time-centred step
+    (lbks_cd_*), and the nuclei, moved by velocity Verlet with the
+    Hellmann-Feynman forces of the instantaneous density, share one time step dt.
+    The solver must hold the electronic ground state at R0 (relaxed there); the
+    electrons start from it (lbks_cd_start).  Step n: R^{n+1} = R^n + V^n dt +
+    F^n dt^2/(2M); the nuclei are set to R^{n+1}; F^{n+1} comes from psi^{n+1};
+    V^{n+1} = V^n + (F^n + F^{n+1}) dt/(2M); then the electrons take the step from
+    psi^{n+1} to psi^{n+2} with the potential of R^{n+1} (centred in time).  With
+    energy_every > 0 the energies are recorded every that many steps
+    (lbks_cd_energy, which also converges V_H).  Every restart_every-th electron
+    step restarts the two-step scheme (energy references re-centred, one-step
+    start), which keeps its parasitic mode from growing while the nuclei move;
+    0 turns the restarts off.  The dynamics is left running; call
+    solver.cd_stop() to return to the relaxation."""
+    M = np.asarray(masses, dtype=np.float64)[:, None]
+    R = np.asarray(R0, dtype=np.float64).reshape(-1, 3).copy()
+    V = np.asarray(V0, dtype=np.float64).reshape(-1, 3).copy()
+    if fixed is not None:
+        V[np.asarray(fixed, dtype=bool)] = 0.0
+    solver.set_nuclei(Z, R)
+    F = _free(solver.forces(), fixed)
+    solver.cd_start(dt, restart_every)
+    ts, Rs, Vs = [0.0], [R.copy()], [V.copy()]
+    et, ep, ek = [], [], []
+
+    def record(k):
+        e = solver.cd_energy()
+        et.append(k * dt)
+        ep.append(float(e["e_total"]))
+        ek.append(0.5 * float(np.sum(M * V * V)))
+
+    if energy_every > 0:
+        record(0)
+    for k in range(n_steps):
+        R = R + V * dt + F / (2.0 * M) * dt * dt
+        solver.set_nuclei(Z, R)
+        Fn = _free(solver.forces(), fixed)
+        V = V + (F + Fn) / (2.0 * M) * dt
+        F = Fn
+        ts.append((k + 1) * dt)
+        Rs.append(R.copy())
+        Vs.append(V.copy())
+        if energy_every > 0 and (k + 1) % energy_every == 0:
+            record(k + 1)
+        if k + 1 < n_steps:
+            solver.cd_step(1)
+    return CDTrajectory(np.array(ts), np.array(Rs), np.array(Vs), np.array(et), np.array(ep), np.array(ek))
+
+
+def vibration_frequency(t: np.ndarray, d: np.ndarray) -> float:
+    """Angular frequency of an oscillating signal from its crossings of the mean of
+    its extremes (linear interpolation between samples; successive crossings are
+    half a period apart); nan with fewer than two crossings."""
+    d = np.asarray(d, dtype=np.float64)
+    x = d - 0.5 * (d.max() + d.min())
+    cr = [t[i] - x[i] * (t[i + 1] - t[i]) / (x[i + 1] - x[i]) for i in range(len(x) - 1)
+          if (x[i] < 0.0) != (x[i + 1] < 0.0)]
+    if len(cr) < 2:
+        return float("nan")
+    return np.pi * (len(cr) - 1) / (cr[-1] - cr[0])

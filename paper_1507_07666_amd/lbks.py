@@ -39,7 +39,7 @@ class lbks_params(Structure):
                 ("softening", c_double), ("init", c_int32), ("init_sigma", c_double),
                 ("init_noise", c_double), ("seed", c_uint64), ("rho_floor", c_double),
                 ("scheme", c_int32), ("stop_checks", c_int32), ("deps_tol", c_double),
-                ("reserved", c_int32 * 4)]
+                ("hermite", c_int32), ("reserved", c_int32 * 3)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -73,6 +73,13 @@ SIGNATURES = {
     "lbks_orbitals": (c_int32, [c_void_p, POINTER(c_double), c_size_t, POINTER(c_double), c_size_t]),
     "lbks_forces": (c_int32, [c_void_p, POINTER(c_double), c_size_t]),
     "lbks_hamiltonian": (c_int32, [c_void_p, POINTER(c_double), c_size_t]),
+    "lbks_relax_sequential": (c_int32, [c_void_p, c_int64, c_double, c_double, c_int32, c_int32,
+                                        POINTER(c_int64), POINTER(c_int32)]),
+    "lbks_cd_start": (c_int32, [c_void_p, c_double, c_int64]),
+    "lbks_cd_step": (c_int32, [c_void_p, c_int64]),
+    "lbks_cd_energy": (c_int32, [c_void_p, POINTER(lbks_energies)]),
+    "lbks_cd_orbitals": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_double), c_size_t]),
+    "lbks_cd_stop": (c_int32, [c_void_p]),
     "lbks_destroy": (None, [c_void_p]),
     "lbks_last_error": (c_char_p, [c_void_p]),
     "lbks_set_potential": (c_int32, [c_void_p, POINTER(c_double)]),
@@ -322,6 +329,40 @@ class Solver:
 
     def orbitals(self):
         return lbks_orbitals(self.ctx)
+
+    def relax_sequential(self, max_steps, dE_tol, deps_tol, check_every=50, max_sweeps=20):
+        """Sequential Gram-Schmidt order (lbks_relax_sequential): (rc, steps, sweeps)."""
+        n = c_int64()
+        sw = c_int32()
+        rc = load().lbks_relax_sequential(self.ctx, int(max_steps), float(dE_tol), float(deps_tol),
+                                          int(check_every), int(max_sweeps), ctypes.byref(n), ctypes.byref(sw))
+        _check(self.ctx, rc, ok=(LBKS_OK, LBKS_NOT_CONVERGED))
+        return rc, n.value, sw.value
+
+    # -- concurrent dynamics (complex orbitals in real time; lbks_cd_*)
+    def cd_start(self, h, restart_every=0):
+        """Start concurrent dynamics with time step h (atomic units); every
+        restart_every-th step restarts the two-step scheme (0: never)."""
+        _check(self.ctx, load().lbks_cd_start(self.ctx, float(h), int(restart_every)))
+
+    def cd_step(self, steps=1):
+        _check(self.ctx, load().lbks_cd_step(self.ctx, int(steps)))
+
+    def cd_energy(self) -> dict:
+        e = lbks_energies()
+        _check(self.ctx, load().lbks_cd_energy(self.ctx, ctypes.byref(e)))
+        return e.as_dict(self.n_orb)
+
+    def cd_orbitals(self):
+        """psi^n as a complex array [n_orb][z][y][x]."""
+        nx, ny, nz = self.p.N[0], self.p.N[1], self.p.N[2]
+        re = np.zeros((self.n_orb, nz, ny, nx))
+        im = np.zeros_like(re)
+        _check(self.ctx, load().lbks_cd_orbitals(self.ctx, _dptr(re), _dptr(im), re.size))
+        return re + 1j * im
+
+    def cd_stop(self):
+        _check(self.ctx, load().lbks_cd_stop(self.ctx))
 
     def hamiltonian(self):
         """(H, Ritz values) of the current state: H_jk = <psi_hat_j|K_h psi_hat_k + S_chi(V psi_hat_k)>."""

@@ -9,7 +9,11 @@ node per axis, float32).  "serve" writes serve.json and serve_rho.npz: every
 point of the seeded serving subset (requests 0-7 of the seed-50 stream on 48^3
 and 64^3 grids: four 8-point geometry scans and four atoms), scan points
 warm-started from the previous point as the server does, with the density on
-every fourth node per axis.
+every fourth node per axis.  "serve_trace" re-runs, the same way, the requests
+holding a point whose relaxation reached the 40000-step limit and adds to each of
+their points the energies checked every 100 steps (Hartree potential as it
+stands), so that a served point is compared with how far the oracle itself moved
+after the step count where the served solve stopped.
 
 The FP32 workloads' references (CH4, H2O, serving) are relaxed with the
 omega = 1 field step of the oracle (Oracle.step_fields), which is the moment of
@@ -103,31 +107,41 @@ def run(name):
           flush=True)
 
 
+def serve_request(r, t0, points, rho4, trace=False):
+    """Relax every point of request r as the server does (scan points warm-started
+    from the previous one); append its records to points and its density to rho4."""
+    o = None
+    for k, sy in enumerate(r.points):
+        if o is None:
+            o = O.oracle_for(sy)
+        else:
+            o.set_nuclei(sy.Z, sy.R)                 # warm start from the previous scan point
+        checks = []
+        rc, steps = o.relax(40000, SERVE_TOL, 100, fields=True,
+                            progress=(lambda n, e: checks.append([int(n), float(e)])) if trace else None)
+        e = o.energies(converge_poisson=True)
+        H, ritz = o.hamiltonian(converge_poisson=False)
+        _, rho = o.state()
+        nx, ny, nz = sy.dims
+        key = f"r{r.rid}_p{k}"
+        rho4[key] = rho.reshape(nz, ny, nx)[::4, ::4, ::4].astype(np.float32)
+        points.append({"rid": r.rid, "point": k, "system": sy.name, "dims": list(sy.dims), "h": sy.h,
+                       "Z": list(sy.Z), "R": [list(x) for x in sy.R], "n_orb": sy.n_orb,
+                       "n_elec": sy.n_elec, "rc": rc, "steps": steps, "energies": energies_dict(e),
+                       "eps": [float(x) for x in e.eps], "ritz": [float(x) for x in ritz],
+                       "rho_l2_sub4": float(np.linalg.norm(rho4[key]))})
+        if trace:
+            points[-1]["checks"] = checks
+        print(f"[serve] r{r.rid} p{k} {sy.name} {sy.dims[0]}^3 rc={rc} steps={steps} E={e.e_total:.10f} "
+              f"({time.time() - t0:.0f}s)", flush=True)
+
+
 def run_serve():
     t0 = time.time()
     reqs = serving_subset()
     points, rho4 = [], {}
     for r in reqs:
-        o = None
-        for k, sy in enumerate(r.points):
-            if o is None:
-                o = O.oracle_for(sy)
-            else:
-                o.set_nuclei(sy.Z, sy.R)             # warm start from the previous scan point
-            rc, steps = o.relax(40000, SERVE_TOL, 100, fields=True)
-            e = o.energies(converge_poisson=True)
-            H, ritz = o.hamiltonian(converge_poisson=False)
-            _, rho = o.state()
-            nx, ny, nz = sy.dims
-            key = f"r{r.rid}_p{k}"
-            rho4[key] = rho.reshape(nz, ny, nx)[::4, ::4, ::4].astype(np.float32)
-            points.append({"rid": r.rid, "point": k, "system": sy.name, "dims": list(sy.dims), "h": sy.h,
-                           "Z": list(sy.Z), "R": [list(x) for x in sy.R], "n_orb": sy.n_orb,
-                           "n_elec": sy.n_elec, "rc": rc, "steps": steps, "energies": energies_dict(e),
-                           "eps": [float(x) for x in e.eps], "ritz": [float(x) for x in ritz],
-                           "rho_l2_sub4": float(np.linalg.norm(rho4[key]))})
-            print(f"[serve] r{r.rid} p{k} {sy.name} {sy.dims[0]}^3 rc={rc} steps={steps} E={e.e_total:.10f} "
-                  f"({time.time() - t0:.0f}s)", flush=True)
+        serve_request(r, t0, points, rho4)
     out = {"requests": SERVE_REQUESTS, "seed": 50, "grids": [48, 64], "scan_points": 8,
            "rule": {"dE_tol": SERVE_TOL, "check_every": 100}, "path": "field step (omega = 1)",
            "points": points, "wall_s": time.time() - t0, "threads": O.max_threads()}
@@ -136,9 +150,32 @@ def run_serve():
     np.savez_compressed(os.path.join(HERE, "serve_rho.npz"), **rho4)
 
 
+def run_serve_trace():
+    """Re-run the requests with a step-limited point and store their check energies
+    (the records must come out as they are stored: same steps and energies)."""
+    t0 = time.time()
+    path = os.path.join(HERE, "serve.json")
+    with open(path) as f:
+        g = json.load(f)
+    reqs = {r.rid: r for r in serving_subset()}
+    limited = sorted({p["rid"] for p in g["points"] if p["rc"] != 0})
+    for rid in limited:
+        points, rho4 = [], {}
+        serve_request(reqs[rid], t0, points, rho4, trace=True)
+        for new in points:
+            old = next(p for p in g["points"] if p["rid"] == rid and p["point"] == new["point"])
+            assert old["steps"] == new["steps"] and old["energies"]["e_total"] == new["energies"]["e_total"], \
+                (rid, new["point"], old["energies"]["e_total"], new["energies"]["e_total"])
+            old["checks"] = new["checks"]
+    with open(path, "w") as f:
+        json.dump(g, f)
+
+
 if __name__ == "__main__":
     for n in sys.argv[1:]:
         if n == "serve":
             run_serve()
+        elif n == "serve_trace":
+            run_serve_trace()
         else:
             run(n)

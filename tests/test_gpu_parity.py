@@ -491,3 +491,77 @@ def test_projected_operator_matches_oracle(L, Z, n, kw):
     e = s.energy()
     assert np.allclose(np.diag(H), e["eps"][:system.n_orb], rtol=0, atol=1e-12 * max(1.0, np.abs(H).max()))
     s.close()
+
+
+@pytest.mark.parametrize("case", ["d1_3", "d0_5", "d0_5_collapsed", "d0_5_fp32", "d0_45_w"])
+def test_fourth_order_weights_match_oracle(L, case):
+    """params.hermite = 4 (fourth-order Hermite equilibrium and source) against the
+    oracle, which derives its weights by solving the moment conditions: D = 1/3
+    (the second-order equilibrium with the node-local source), D = 1/2 (the
+    largest stable D, a 1.5 times longer time step), the omega = 1 field update,
+    FP32 bulk, and the paper's orthogonalisation source."""
+    system = I.ne_atom().scaled(20)
+    kw = {"d1_3": dict(D=1.0 / 3.0), "d0_5": dict(D=0.5), "d0_5_collapsed": dict(D=0.5, scheme=1),
+          "d0_5_fp32": dict(D=0.5, precision=1), "d0_45_w": dict(D=0.45, ortho=1)}[case]
+    say("hermite 4", case)
+    p = L.params_for(system, init=L.LBKS_INIT_USER, hermite=4, **kw)
+    s = L.Solver(p)
+    s.set_nuclei(system.Z, system.R)
+    s.set_orbitals(system.psi0())
+    o = O.oracle_for(system, hermite=4, D=p.D, ortho=ORTHO[p.ortho])
+    s.relax(30)
+    for _ in range(30):
+        o.step()
+    if kw.get("precision"):
+        _, rho = s.orbitals()
+        _, rho_o = o.state()
+        assert np.linalg.norm(rho.ravel() - rho_o) <= 1e-5 * np.linalg.norm(rho_o)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-6)
+    else:
+        compare_state(s, o, 1e-10, 1e-10)
+        compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["fixed_potential", "beryllium_scf"])
+def test_sequential_gram_schmidt_matches_oracle(L, case):
+    """lbks_relax_sequential (orbitals relaxed one after another on the omega = 1
+    field update) against the oracle's relax_sequential (population steps with the
+    other orbitals frozen; at omega = 1 the same moments): the same stopping step
+    and sweep count, and the same orbitals.  A fixed low-symmetry anisotropic well
+    (three separated levels) and a self-consistent Be atom (two orbitals)."""
+    from paper_1507_07666_amd.inputs import node_coords
+    say("sequential", case)
+    if case == "fixed_potential":
+        dims, h, n = (12, 12, 12), 0.35, 3
+        nx, ny, nz = dims
+        x, y, z = node_coords(nx, h), node_coords(ny, h), node_coords(nz, h)
+        V = (0.5 * (4.0 * x[None, None, :] ** 2 + 2.25 * y[None, :, None] ** 2 + z[:, None, None] ** 2)).ravel()
+        V = V + 0.2 * np.sin(np.arange(V.size) * 0.37)
+        rng = np.random.default_rng(3)
+        psi0 = rng.standard_normal((n, nz, ny, nx))
+        p = L.params(dims, h, n, 2 * n, init=L.LBKS_INIT_USER, scheme=L.LBKS_SCHEME_COLLAPSED, xc=L.LBKS_XC_NONE,
+                     hartree=0)
+        s = L.Solver(p)
+        s.set_potential(V)
+        s.set_orbitals(psi0)
+        o = O.Oracle(O.Params(dims, h, n, 2 * n, xc=O.XC_NONE, hartree=False))
+        o.set_potential(V)
+        o.set_orbitals(psi0.reshape(n, -1))
+        args = (60000, 1e-12, 1e-12, 50, 4)
+    else:
+        system = I.atom(4, 16, h=0.35, softening=0.3, seed=4)
+        p = L.params_for(system, init=L.LBKS_INIT_USER, scheme=L.LBKS_SCHEME_COLLAPSED)
+        s = L.Solver(p)
+        s.set_nuclei(system.Z, system.R)
+        s.set_orbitals(system.psi0())
+        o = O.oracle_for(system)
+        args = (40000, 1e-9, 1e-9, 50, 12)
+    rc, steps, sweeps = s.relax_sequential(*args)
+    rco, steps_o, sweeps_o = O.relax_sequential(o, *args)
+    say(f"sequential {case}: gpu rc {rc} steps {steps} sweeps {sweeps}; oracle {rco} {steps_o} {sweeps_o}")
+    assert (rc, steps, sweeps) == (rco, steps_o, sweeps_o)
+    assert rc == L.LBKS_OK
+    compare_state(s, o, 1e-10, 1e-9)
+    compare_energy(s.energy(), o.energies(converge_poisson=True), 1e-10)
+    s.close()

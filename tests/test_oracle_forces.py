@@ -117,3 +117,38 @@ def test_h2_force_matches_energy_derivative(oracle_mod):
     # the atom at +d/2 moves with d/2: F_2x = -dE/dR_2x = -dE/dd
     assert F[1, 0] > 0.0                                  # repulsive at 1.4 bohr with a = 0.3
     assert abs(F[1, 0] + dEdd) <= 3e-3 * abs(dEdd), (F[1, 0], -dEdd)
+
+
+@pytest.mark.parametrize("hermite", [2, 4])
+def test_fourth_order_source_makes_the_fixed_point_variational(oracle_mod, hermite):
+    """One electron on two protons (Hartree and xc off): with the fourth-order
+    source the potential acts at the node, the relaxation operator
+    K_h + V is symmetric and its lowest eigenvalue is a variational energy, so the
+    Hellmann-Feynman force equals -dE/dR to the accuracy of the difference quotient;
+    the second-order source smears V over the neighbours (S_chi(V .)) and leaves a
+    difference of order 1e-3."""
+    O = oracle_mod
+
+    def system(d):
+        return I.System("H2+", (24, 24, 24), 0.3, [1.0, 1.0], [(-d / 2, 0.0, 0.0), (d / 2, 0.0, 0.0)], 1, 1, 0.3,
+                        seed=7)
+
+    def relaxed(d, psi=None):
+        o = O.oracle_for(system(d), hermite=hermite, hartree=False, xc=O.XC_NONE)
+        if psi is not None:
+            o.set_orbitals(psi)
+        assert o.relax(40000, 1e-13, 50)[0] == 0
+        return o
+
+    d0 = 2.0
+    o = relaxed(d0)
+    F = o.forces()[1, 0]
+    psi = o.state()[0].reshape(1, 24, 24, 24)
+    g = {dd: (relaxed(d0 + dd, psi).energies(converge_poisson=False).e_total
+              - relaxed(d0 - dd, psi).energies(converge_poisson=False).e_total) / (2 * dd) for dd in (0.01, 0.02)}
+    dEdd = g[0.01] + (g[0.01] - g[0.02]) / 3.0
+    rel = abs(F + dEdd) / abs(dEdd)
+    if hermite == 4:
+        assert rel < 1e-5, rel
+    else:
+        assert 3e-4 < rel < 3e-3, rel
