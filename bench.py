@@ -419,7 +419,9 @@ def main():
         tkey = f"{args.workload}_{args.precision}_" + (f"v{variant}" if scheme == 0 else "collapsed" if bricks else "")
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(tkey) if tkey else None,
-                           "kernel": "k_stream_collide" if scheme == 0 else "k_collapsed_brick" if bricks else "k_collapsed",
+                           "kernel": ("k_stream_collide_wide" if variant is not None and variant & 8 and system.n_orb <= 5
+                                      else "k_stream_collide") if scheme == 0
+                           else "k_collapsed_brick" if bricks else "k_collapsed",
                            "avg_us": avg_s * 1e6, "launches": k1_n, "alg_bytes_per_launch": alg}
         # the same bytes against what a plain copy kernel reaches on this GPU
         cp = copy_calibration(678 << 20, 20)
