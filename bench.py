@@ -367,11 +367,9 @@ def main():
     if args.warmup:
         solver.relax(args.warmup)
     # the LDS-staged field update (collapsed scheme, Gram-Schmidt, at most five
-    # orbitals) has a single form: nothing to tune
+    # orbitals) tunes its brick depth and workgroup order
     bricks = scheme == lbks.LBKS_SCHEME_COLLAPSED and system.n_orb <= 5 and ortho == lbks.LBKS_ORTHO_GS
-    if bricks:
-        variant, tune_ms = None, None
-    elif args.no_autotune or args.variant is not None:
+    if args.no_autotune or args.variant is not None:
         variant, tune_ms = solver.variant(), None
     else:
         variant, tune_ms = solver.autotune(reps=5, force=True)

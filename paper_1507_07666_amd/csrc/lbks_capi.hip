@@ -610,6 +610,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.ntile_ghost = h.ntile_ghost;
     pl.ntile_sor = h.ntile_sor;
     pl.ntile_brick = h.ntile_brick;
+    for (int k = 0; k < 4; ++k) pl.nbrick[k] = bricks_of(h.nx, h.ny, h.nz, brick_depth(k));
     pl.brick_partials = brick_partials(h.ntile, h.ntile_brick);
     pl.n_inst = 1;
     pl.variant = default_variant(pl.precision);
@@ -1458,7 +1459,7 @@ int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
             o.n_site += h.ntile;
             o.n_ghost += h.ntile_ghost;
             o.n_sor += h.ntile_sor;
-            o.n_brick += h.ntile_brick;
+            o.n_brick += bricks_of(h.nx, h.ny, h.nz, brick_depth(g.variant));
             o.n_site_w += (h.ntile + kw - 1) / kw;
         }
         o.desc = take(sizeof(InstDesc) * g.members.size());
@@ -1509,7 +1510,7 @@ int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
             for (int t = 0; t < d.ntile; ++t) ts[ns++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_ghost; ++t) tg[ng++] = make_int2((int)q, t);
             for (int t = 0; t < d.ntile_sor; ++t) tr[nr++] = make_int2((int)q, t);
-            for (int t = 0; t < d.ntile_brick; ++t) tb[nb++] = make_int2((int)q, t);
+            for (int t = 0; t < bricks_of(d.nx, d.ny, d.nz, brick_depth(g.variant)); ++t) tb[nb++] = make_int2((int)q, t);
             for (int t = 0; t < (d.ntile + kw - 1) / kw; ++t) tw[nw++] = make_int2((int)q, t);
             all_brick = all_brick && brick_partials(d.ntile, d.ntile_brick);
             ti[q] = (int)q;

@@ -304,32 +304,38 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
 
 // The same omega = 1 update (Gram-Schmidt mode, psi* = psi_hat) with the fields
 // staged in LDS: a workgroup owns a brick of BX x BY nodes in x, y and marches
-// over BZ planes in z, keeping three planes of psi_hat_j and V with a one-node
-// halo in a ring (the plane after next is fetched into registers while a plane
-// is computed), so each field value is fetched twice per brick (planes z0 - 1 to
-// z0 + 2 for two computed planes) instead of once per neighbour; the loads are
-// global, not flat, so several stay in flight.  The terms are added in the same
-// order as in k_collapsed; terms from outside the box are exact zeros there and
-// skipped here, so the new orbitals are the same.  The overlap partial of the
-// brick (psi_j psi_k summed over its nodes in FP64, the planes in order) goes to
-// tile slot b when the instance has no more bricks than node tiles (slots from
-// the brick count on are zeroed by the bricks in turn); otherwise k_overlap_psi
-// writes the partials.
-template <typename T, int NO>
-__global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restrict__ descs,
-                                                        const int2 *__restrict__ bricks)
+// over DZ planes in z (DZ = 8, 12, 16 or 24, the brick variant).  Each plane of
+// psi_hat_j and V, with a one-node halo, goes through one of two LDS slots (the
+// plane after it is fetched into registers meanwhile), and each thread reads the
+// 3 x 3 neighbourhood of its column in that plane once: the in-plane terms go to
+// the output node in the same plane, the terms with v_z = +-1 (the five offsets
+// of the plus shape) to the nodes above and below, held in a register queue of
+// three output planes.  An output plane is complete, and written, once the plane
+// above it has been read: 9 x (NO + 1) LDS reads per plane instead of 19 per
+// field and node.  Terms from outside the box are exact zeros in LDS.  The
+// overlap partial of the brick (psi_j psi_k summed over its nodes in FP64, the
+// planes in order) goes to tile slot b when the instance has no more bricks of
+// the shallowest depth than node tiles (the slots from the brick count on are zeroed by the
+// bricks in turn); otherwise k_overlap_psi writes the partials.
+template <typename T, int NO, int DZ>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_collapsed_brick(const InstDesc *__restrict__ descs,
+                                                        const int2 *__restrict__ bricks, int linear)
 {
     constexpr int PX = BX + 2, PY = BY + 2, PL = PX * PY;
     constexpr int NL = (PL + BS - 1) / BS;         // plane positions per thread
-    __shared__ T lds[NO + 1][3][PL];              // psi_hat_0 .. psi_hat_{NO-1}, V; three planes
-    const TileRef tr = resolve(bricks);
+    __shared__ T lds[2][NO + 1][PL];              // psi_hat_0 .. psi_hat_{NO-1}, V; two plane slots
+    const TileRef tr = resolve(bricks, linear);
     const InstDesc &d = descs[tr.inst];
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     const int gx = (nx + BX - 1) / BX, gy = (ny + BY - 1) / BY;
+    const int nb = bricks_of(nx, ny, nz, DZ);
     const int b = tr.tile;
-    const int x0 = (b % gx) * BX, y0 = ((b / gx) % gy) * BY, z0 = (b / (gx * gy)) * BZ;
+    if (b >= nb) return;                           // uniform per workgroup, before any barrier
+    const int x0 = (b % gx) * BX, y0 = ((b / gx) % gy) * BY, z0 = (b / (gx * gy)) * DZ;
+    const int zlast = min(z0 + DZ, nz) - 1;        // last output plane of the brick
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     const int x = x0 + tx, y = y0 + ty;
+    const bool mine = x < nx && y < ny;
     const size_t N = (size_t)d.nsite;
     const auto *__restrict__ ph = gmem((const T *)d.psihat);
     const auto *__restrict__ Vp = gmem((const T *)d.V);
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
             cdc[c] = dt * (T)d.chi[rep[c]];
         }
     }
-    // one plane (zero outside the box) into registers, then into a ring slot
+    // one plane (zero outside the box) into registers, then into an LDS slot
     T pre[NL][NO + 1];
     auto fetch = [&](int z) {
 #pragma unroll
@@ -366,65 +372,81 @@ __global__ __launch_bounds__(BS) void k_collapsed_brick(const InstDesc *__restri
             const int i = (int)threadIdx.x + q * BS;
             if (i < PL)
 #pragma unroll
-                for (int j = 0; j <= NO; ++j) lds[j][slot][i] = pre[q][j];
+                for (int j = 0; j <= NO; ++j) lds[slot][j][i] = pre[q][j];
         }
     };
-    fetch(z0 - 1);
-    store(0);
-    fetch(z0);
-    store(1);
-    fetch(z0 + 1);
-    store(2);
-    fetch(z0 + 2);
-    __syncthreads();
+    // register queue: lo = output plane zp - 1 (complete after plane zp), mid = zp, hi = zp + 1
+    T lo[NO], mid[NO], hi[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) lo[j] = mid[j] = hi[j] = (T)0;
     double prod[NO * (NO + 1) / 2];
 #pragma unroll
     for (int q = 0; q < NO * (NO + 1) / 2; ++q) prod[q] = 0.0;
-    for (int k = 0; k < BZ; ++k) {
-        const int z = z0 + k;
-        if (z >= nz) break;                         // the same for the whole workgroup
-        if (x < nx && y < ny) {
-            T acc[NO];
+    fetch(z0 - 1);
+    for (int zp = z0 - 1; zp <= zlast + 1; ++zp) {
+        const int slot = (zp - z0 + 1) & 1;
+        store(slot);                                // this slot was last read two planes ago
+        if (zp <= zlast) fetch(zp + 1);             // in flight while this plane is read
+        __syncthreads();
+        if (mine) {
 #pragma unroll
-            for (int j = 0; j < NO; ++j) acc[j] = (T)0;
-            // a departure node outside the box holds zeros in LDS, so its term adds
-            // exactly nothing (no per-direction test is needed)
+            for (int oy = -1; oy <= 1; ++oy) {
+                // one row of three offsets at a time: no LDS read moves across rows (register
+                // pressure), and no inner loop whose registers would be shuffled around the
+                // plane in flight (which would wait for it)
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int p = 0; p < Q; ++p) {
-                const int vx = VX(p), vy = VY(p), vz = VZ(p);
-                const int c = vx * vx + vy * vy + vz * vz;
-                const int slot = (k + 1 - vz + 3) % 3;
-                const int li = (ty + 1 - vy) * PX + (tx + 1 - vx);
-                const T dp = cdc[c] * lds[NO][slot][li];
+                for (int ox = -1; ox <= 1; ++ox) {
+                    // the departure node (x + ox, y + oy) of the velocities (-ox, -oy, v_z)
+                    const int li = (ty + 1 + oy) * PX + (tx + 1 + ox);
+                    const T vn = lds[slot][NO][li];
+                    const int c = ox * ox + oy * oy;
+                    const T w0 = cxi[c] - cdc[c] * vn;           // v_z = 0: the node in this plane
+                    if (c <= 1) {
+                        const T w1 = cxi[c + 1] - cdc[c + 1] * vn;   // v_z = +1 above, v_z = -1 below
 #pragma unroll
-                for (int j = 0; j < NO; ++j) acc[j] += (cxi[c] - dp) * lds[j][slot][li];
+                        for (int j = 0; j < NO; ++j) {
+                            const T u = lds[slot][j][li];
+                            mid[j] += w0 * u;
+                            hi[j] += w1 * u;
+                            lo[j] += w1 * u;
+                        }
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < NO; ++j) mid[j] += w0 * lds[slot][j][li];
+                    }
+                }
             }
-            const size_t s = ((size_t)z * ny + y) * nx + x;
-            if (d.active != ~0u) {                  // sequential order: frozen orbitals keep their fields
+            __builtin_amdgcn_sched_barrier(0);
+            const int z = zp - 1;
+            if (z >= z0) {                          // output plane z is complete
+                const size_t s = ((size_t)z * ny + y) * nx + x;
+                if (d.active != ~0u) {              // sequential order: frozen orbitals keep their fields
+#pragma unroll
+                    for (int j = 0; j < NO; ++j)
+                        if (!((d.active >> j) & 1u)) lo[j] = psi[(size_t)j * N + s];
+                }
+#pragma unroll
+                for (int j = 0; j < NO; ++j) psi[(size_t)j * N + s] = lo[j];
+                int q = 0;
 #pragma unroll
                 for (int j = 0; j < NO; ++j)
-                    if (!((d.active >> j) & 1u)) acc[j] = psi[(size_t)j * N + s];
+#pragma unroll
+                    for (int kk = 0; kk <= j; ++kk) prod[q++] += (double)lo[j] * (double)lo[kk];
             }
 #pragma unroll
-            for (int j = 0; j < NO; ++j) psi[(size_t)j * N + s] = acc[j];
-            int q = 0;
-#pragma unroll
-            for (int j = 0; j < NO; ++j)
-#pragma unroll
-                for (int kk = 0; kk <= j; ++kk) prod[q++] += (double)acc[j] * (double)acc[kk];
+            for (int j = 0; j < NO; ++j) {
+                lo[j] = mid[j];
+                mid[j] = hi[j];
+                hi[j] = (T)0;
+            }
         }
-        __syncthreads();                            // slot k % 3 (plane z - 1) is no longer read
-        if (k + 1 < BZ) {
-            store(k % 3);                           // plane z + 2, fetched one plane ago
-            fetch(z + 3);                           // in flight while plane z + 1 is computed
-        }
-        __syncthreads();
     }
     if (brick_partials(d.ntile, d.ntile_brick)) {   // uniform per workgroup
         const int np = NO * (NO + 1) / 2;
         block_sum_store(prod, np, d.s_part + b, d.ntile);
         if ((int)threadIdx.x < np)
-            for (int t = d.ntile_brick + b; t < d.ntile; t += d.ntile_brick) d.s_part[(size_t)threadIdx.x * d.ntile + t] = 0.0;
+            for (int t = nb + b; t < d.ntile; t += nb) d.s_part[(size_t)threadIdx.x * d.ntile + t] = 0.0;
     }
 }
 
@@ -481,17 +503,26 @@ int launch_stream_collide(const Plan &pl, int parity, hipStream_t st)
 }
 
 // Gram-Schmidt mode with at most five orbitals: the LDS-staged brick update (with
-// the overlap partials, or followed by them); otherwise the node-per-thread update
-// with the fused overlap partials, in the autotuned variant.
+// the overlap partials, or followed by them), its depth (variant bits 0 and 1) and
+// workgroup order (bit 2) autotuned; otherwise the node-per-thread update with the
+// fused overlap partials, in the autotuned variant.
 bool collapsed_uses_bricks(const Plan &pl) { return !pl.wmode && pl.no <= 5; }
 
 int launch_collapsed_update(const Plan &pl, hipStream_t st)
 {
     if (collapsed_uses_bricks(pl)) {
+        const int linear = (pl.variant >> 2) & 1;
         const int e = dispatch_tn(pl, [&](auto tg) {
             using TG = decltype(tg);
             if constexpr (TG::NO <= 5) {
-                k_collapsed_brick<typename TG::T, TG::NO><<<grid_brick(pl), BS, 0, st>>>(pl.d_desc, pl.tt.brick);
+                using T = typename TG::T;
+                const int g = grid_brick(pl);
+                switch (brick_depth(pl.variant)) {
+                case 8: k_collapsed_brick<T, TG::NO, 8><<<g, BS, 0, st>>>(pl.d_desc, pl.tt.brick, linear); break;
+                case 12: k_collapsed_brick<T, TG::NO, 12><<<g, BS, 0, st>>>(pl.d_desc, pl.tt.brick, linear); break;
+                case 16: k_collapsed_brick<T, TG::NO, 16><<<g, BS, 0, st>>>(pl.d_desc, pl.tt.brick, linear); break;
+                default: k_collapsed_brick<T, TG::NO, 24><<<g, BS, 0, st>>>(pl.d_desc, pl.tt.brick, linear); break;
+                }
                 return (int)hipGetLastError();
             } else {
                 return (int)hipErrorInvalidValue;

@@ -534,7 +534,7 @@ int dispatch_tt(const Plan &pl, F &&f)
 static inline int grid_site(const Plan &pl) { return pl.tt.site ? pl.tt.n_site : pl.ntile; }
 static inline int grid_ghost(const Plan &pl) { return pl.tt.ghost ? pl.tt.n_ghost : pl.ntile_ghost; }
 static inline int grid_sor(const Plan &pl) { return pl.tt.sor ? pl.tt.n_sor : pl.ntile_sor; }
-static inline int grid_brick(const Plan &pl) { return pl.tt.brick ? pl.tt.n_brick : pl.ntile_brick; }
+static inline int grid_brick(const Plan &pl) { return pl.tt.brick ? pl.tt.n_brick : pl.nbrick[pl.variant & 3]; }
 static inline int grid_inst(const Plan &pl) { return pl.tt.inst ? pl.tt.n_inst : 1; }
 static inline int grid_group(const Plan &pl) { return RG * grid_inst(pl); }
 

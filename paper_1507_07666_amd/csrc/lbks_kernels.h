@@ -19,15 +19,19 @@ constexpr int MAXO = 16;       // orbital capacity of the descriptor
 constexpr int NMOM = 10;       // q, p_xyz, Q_xx Q_yy Q_zz Q_xy Q_xz Q_yz
 constexpr int NEBASE = 5;      // rho V_ext, rho V_H, rho eps_x, rho eps_c, rho
 constexpr int RCH = 8;         // partial arrays hold whole chunks of RCH columns
-constexpr int BX = 32, BY = 8, BZ = 2;   // brick of the LDS-staged omega = 1 update (BX * BY = BS)
+constexpr int BX = 32, BY = 8, BZ = 8;   // brick of the LDS-staged omega = 1 update (BX * BY = BS);
+                                         // BZ is the shallowest of its depths
 
-__host__ __device__ constexpr int bricks_of(int nx, int ny, int nz)
+__host__ __device__ constexpr int bricks_of(int nx, int ny, int nz, int bz = BZ)
 {
-    return ((nx + BX - 1) / BX) * ((ny + BY - 1) / BY) * ((nz + BZ - 1) / BZ);
+    return ((nx + BX - 1) / BX) * ((ny + BY - 1) / BY) * ((nz + bz - 1) / bz);
 }
+// Depth in z of the bricks for an update-kernel variant (bits 0 and 1): 8, 12, 16, 24.
+__host__ __device__ constexpr int brick_depth(int variant) { return BZ + 4 * (variant & 3) + 4 * ((variant & 3) == 3); }
 // The brick update writes the overlap partials itself (brick b into tile slot b,
-// the slots past the last brick zero) when an instance has no more bricks than
-// node tiles; otherwise a separate pass over the node tiles writes them.
+// the slots past the last brick zero) when an instance has no more bricks of the
+// shallowest depth than node tiles, so for every depth; otherwise a separate pass
+// over the node tiles writes them.
 __host__ __device__ constexpr bool brick_partials(int ntile, int nbrick) { return nbrick <= ntile; }
 constexpr int NUCG = 16;       // nuclei per force-kernel pass
 constexpr int MAXNUC = 64;     // nuclei per solve (LBKS_MAX_NUC)
@@ -56,7 +60,7 @@ struct InstDesc {
     int ntile;                 // site tiles of BS nodes
     int ntile_ghost;           // tiles over the six ghost faces
     int ntile_sor;             // tiles over one colour of the SOR sweep
-    int ntile_brick;           // BX x BY x BZ bricks of the omega = 1 field update
+    int ntile_brick;           // BX x BY x BZ bricks (the shallowest depth) of the omega = 1 field update
     int ortho, xc, hartree, precision;
     int scheme;
     int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
@@ -109,10 +113,12 @@ struct Plan {
     bool wmode = false;
     bool gga = false;     // gradient-corrected exchange-correlation (needs the k_gga pass)
     int ntile = 0, ntile_ghost = 0, ntile_sor = 0, ntile_brick = 0;   // single-instance counts
+    int nbrick[4] = {0, 0, 0, 0};   // single-instance bricks of each depth (brick_depth of variant bits 0, 1)
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave
                           // occupancy, bit 2 workgroups in dispatch order, bit 3 16 bytes of nodes per lane
-                          // in the population update (buckets up to five orbitals; bits 0 and 1 then unused)
+                          // in the population update (buckets up to five orbitals; bits 0 and 1 then unused);
+                          // the brick update reads bits 0 and 1 as its depth and bit 2 as its order
     bool brick_partials = true;   // every instance gets its overlap partials from the brick update
 };
 

@@ -145,13 +145,17 @@ def test_gradient_corrected_xc_matches_oracle(L, case):
     s.close()
 
 
-@pytest.mark.parametrize("n", [20, 19])
-def test_collapsed_scheme_matches_population_oracle(L, n):
-    """20^3: the brick update writes the overlap partials (30 bricks, 32 node tiles);
-    19^3: more bricks (30) than node tiles (27), so a separate pass writes them."""
-    system = I.ne_atom().scaled(n)
-    say("collapsed scheme", n)
+@pytest.mark.parametrize("dims,variant", [((20, 20, 20), v) for v in range(8)] + [((6, 17, 17), 0), ((6, 17, 17), 7)])
+def test_collapsed_scheme_matches_population_oracle(L, dims, variant):
+    """The brick update in each of its variants (depth 8, 12, 16, 24 in z, bits 0-1;
+    dispatch order, bit 2).  20^3: the bricks write the overlap partials (9 bricks of
+    the shallowest depth, 32 node tiles), and depths 8 and 12 leave a ragged last
+    brick; 6 x 17 x 17: more bricks (9) than node tiles (7), so a separate pass
+    writes them."""
+    system = non_cubic(I.ne_atom(), dims)
+    say("collapsed scheme", dims, "variant", variant)
     s, o = make_pair(L, system, scheme=L.LBKS_SCHEME_COLLAPSED)
+    s.set_variant(variant)
     s.relax(40)
     for _ in range(40):
         o.step()

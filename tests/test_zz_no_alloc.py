@@ -83,14 +83,15 @@ def test_static_workspace_equals_allocating_relax_twice(L):
 
 
 def test_static_workspace_refuses_oversized_tables(L):
-    """Sixteen 128^3 members (omega = 1 field update, no populations) need about
-    2.4 MB of tables, more than the 2 MiB workspace."""
-    systems = [(I.he_atom().scaled(128, h=0.15), dict(precision=1, scheme=1)) for _ in range(16)]
+    """Twenty 128^3 members (omega = 1 field update, no populations) need about
+    2.4 MB of tables (118 KB each: site, ghost, SOR, brick and wide-update tile
+    entries), more than the 2 MiB workspace."""
+    systems = [(I.he_atom().scaled(128, h=0.15), dict(precision=1, scheme=1)) for _ in range(20)]
     b, members = make_batch(L, systems)
     say("oversized batch")
     with pytest.raises(L.LbksError) as ex:
         b.relax(5, static=True)
     assert "static workspace" in str(ex.value) and ex.value.code == L.LBKS_E_INVAL
     st, k = b.relax(5)                      # the allocating call still serves this batch
-    assert k == [5] * 16
+    assert k == [5] * 20
     b.close()
