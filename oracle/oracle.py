@@ -28,7 +28,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblbks_oracle.so")
+# LBKS_ORACLE_LIB points the loader at another build of lbks_oracle.c (the
+# sanitizer test's instrumented one)
+LIB_PATH = os.environ.get("LBKS_ORACLE_LIB") or os.path.join(_HERE, "liblbks_oracle.so")
 SRC_PATH = os.path.join(_HERE, "lbks_oracle.c")
 
 XC_NONE, XC_X, XC_X_LYPLOCAL, XC_X_PZ81, XC_B88_LYP, XC_B88_LYP_POLARISED = 0, 1, 2, 3, 4, 5
