@@ -379,13 +379,16 @@ int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *l
  * workgroups in dispatch order instead of giving each XCD one contiguous range
  * of tiles, bit 3 gives each lane of the population update 16 bytes of
  * x-consecutive nodes (2 in FP64, 4 in FP32) read and written with one access
- * per plane (orbital buckets of at most five; bits 0 and 1 are then unused, and
- * larger buckets ignore bit 3).  Every variant computes the same per-node
- * arithmetic; the overlap's summation order differs with bits 0 and 3, and the
- * compiler may contract a product into a fused multiply-add differently in the
- * wide form (last-bit differences); bit 2 changes nothing in the results.  The
- * LDS-staged omega = 1 update (Gram-Schmidt, at most five orbitals) has one form
- * and ignores the variant; the collapsed node-per-lane update ignores bit 3.
+ * per plane (orbital buckets of at most five; bit 0 then rolls its loop over the
+ * 19 directions, which trades overlap between directions for four times the
+ * waves, bit 1 is unused, and larger buckets ignore bit 3).  Every variant
+ * computes the same per-node arithmetic; the overlap's summation order differs
+ * with bits 0 and 3, and the compiler may contract a product into a fused
+ * multiply-add differently in the wide form (last-bit differences); bit 2
+ * changes nothing in the results.  The LDS-staged omega = 1 update
+ * (Gram-Schmidt, at most five orbitals) reads bits 0 and 1 as its brick depth in
+ * z (8, 12, 16, 24 nodes) and bit 2 as its workgroup order; the collapsed
+ * node-per-lane update ignores bit 3.
  * Defaults: 4 for FP64, 3 for FP32.  lbks_set_variant: LBKS_E_INVAL outside
  * 0..15. */
 int lbks_set_variant(lbks_ctx *ctx, int32_t variant);

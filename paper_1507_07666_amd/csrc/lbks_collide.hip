@@ -119,9 +119,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(waves_hint<V
 // 16-byte access per plane serves the lane (at any element offset; planes are read
 // through guarded resources).  Workgroup w covers K node tiles; its overlap partial
 // goes to tile slot K w and the other K - 1 slots are zeroed.  The arithmetic per
-// node is that of k_stream_collide.  Variant bit 2 (dispatch order) applies; the
-// overlap partial is always the wave-halving form.
-template <typename T, int NO, bool W>
+// node is that of k_stream_collide.  Variant bit 2 (dispatch order) applies, bit 0
+// rolls the loop over the directions; the overlap partial is always the
+// wave-halving form.
+template <typename T, int NO, bool W, bool ROLL>
 __global__ __launch_bounds__(BS) void k_stream_collide_wide(const InstDesc *__restrict__ descs,
                                                             const int2 *__restrict__ tiles, int parity, int linear)
 {
@@ -161,8 +162,7 @@ __global__ __launch_bounds__(BS) void k_stream_collide_wide(const InstDesc *__re
     for (int j = 0; j < NO; ++j)
 #pragma unroll
         for (int i = 0; i < K; ++i) acc[j][i] = (T)0;
-#pragma unroll
-    for (int p = 0; p < Q; ++p) {
+    auto direction = [&](int p) {
         const int vx = VX(p), vy = VY(p), vz = VZ(p);
         bool ok[K];
 #pragma unroll
@@ -216,6 +216,16 @@ __global__ __launch_bounds__(BS) void k_stream_collide_wide(const InstDesc *__re
                 }
             }
         }
+    };
+    // unrolled, the compiler overlaps the directions but keeps a whole workgroup's
+    // worth of registers per wave (one wave per SIMD); rolled, four waves per SIMD
+    // keep more loads in flight
+    if constexpr (ROLL) {
+#pragma unroll 1
+        for (int p = 0; p < Q; ++p) direction(p);
+    } else {
+#pragma unroll
+        for (int p = 0; p < Q; ++p) direction(p);
     }
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
@@ -480,8 +490,13 @@ static int launch_stream_collide_wide(const Plan &pl, int parity, hipStream_t st
         if constexpr (TG::NO <= 5) {
             constexpr int K = 16 / (int)sizeof(typename TG::T);
             const int grid = pl.tt.site_w ? pl.tt.n_site_w : (pl.ntile + K - 1) / K;
-            k_stream_collide_wide<typename TG::T, TG::NO, TG::W><<<grid, BS, 0, st>>>(pl.d_desc, pl.tt.site_w, parity,
-                                                                                     (pl.variant >> 2) & 1);
+            const int linear = (pl.variant >> 2) & 1;
+            if (pl.variant & 1)
+                k_stream_collide_wide<typename TG::T, TG::NO, TG::W, true><<<grid, BS, 0, st>>>(pl.d_desc, pl.tt.site_w,
+                                                                                               parity, linear);
+            else
+                k_stream_collide_wide<typename TG::T, TG::NO, TG::W, false><<<grid, BS, 0, st>>>(pl.d_desc, pl.tt.site_w,
+                                                                                                parity, linear);
             return (int)hipGetLastError();
         } else {
             return (int)hipErrorInvalidValue;

@@ -117,7 +117,8 @@ struct Plan {
     int n_inst = 1;
     int variant = 0;      // update-kernel variant (autotuned): bit 0 matrix-core overlap, bit 1 8-wave
                           // occupancy, bit 2 workgroups in dispatch order, bit 3 16 bytes of nodes per lane
-                          // in the population update (buckets up to five orbitals; bits 0 and 1 then unused);
+                          // in the population update (buckets up to five orbitals; bit 0 then rolls its loop
+                          // over the directions, bit 1 is unused);
                           // the brick update reads bits 0 and 1 as its depth and bit 2 as its order
     bool brick_partials = true;   // every instance gets its overlap partials from the brick update
 };
@@ -133,7 +134,7 @@ constexpr int wide_nodes(int elem_bytes) { return 16 / elem_bytes; }
 // both workgroup orders when it applies (its bits 0 and 1 change nothing)
 inline bool variant_distinct(int v, int no, bool populations)
 {
-    return v < 8 || (populations && no <= 5 && (v & 3) == 0);
+    return v < 8 || (populations && no <= 5 && (v & 2) == 0);
 }
 
 int orbital_bucket(int n_orb);

@@ -383,12 +383,14 @@ def test_dispatch_order_bit_changes_no_result(L, prec):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("case", ["ragged_19", "w_mode", "non_cubic_fp32", "omega0.8_3orb", "batch"])
-def test_wide_population_update_matches_oracle(L, case):
-    """The wide population update (variant bit 3) on grids whose node count is not a
-    multiple of the nodes per lane (19^3 = 6859; 30 x 22 x 13 in FP32 has rows of 30
-    nodes, so runs cross rows), in the paper's orthogonalisation mode, at omega != 1
-    with three orbitals, and as batch members next to node-per-lane members."""
+@pytest.mark.parametrize("case,variant", [(c, v) for c in ("ragged_19", "w_mode", "non_cubic_fp32", "omega0.8_3orb")
+                                          for v in (12, 13)] + [("batch", None)])
+def test_wide_population_update_matches_oracle(L, case, variant):
+    """The wide population update (variant bit 3), its direction loop unrolled (12)
+    and rolled (13), on grids whose node count is not a multiple of the nodes per
+    lane (19^3 = 6859; 30 x 22 x 13 in FP32 has rows of 30 nodes, so runs cross
+    rows), in the paper's orthogonalisation mode, at omega != 1 with three orbitals,
+    and as batch members (unrolled and rolled) next to node-per-lane members."""
     say("wide", case)
     if case == "batch":
         systems = [(I.ne_atom().scaled(19), dict(precision=0)), (I.atom(5, 17, h=0.35, seed=4), dict(precision=1)),
@@ -399,7 +401,7 @@ def test_wide_population_update_matches_oracle(L, case):
             m = b.add(L.params_for(sy, init=L.LBKS_INIT_USER, **kw))
             m.set_nuclei(sy.Z, sy.R)
             m.set_orbitals(sy.psi0())
-            m.set_variant(8 if k != 2 else 4)
+            m.set_variant((8, 9, 4)[k])
             members.append(m)
         b.relax(12, dE_tol=0.0, check_every=6)
         for (sy, kw), m in zip(systems, members):
@@ -422,7 +424,7 @@ def test_wide_population_update_matches_oracle(L, case):
                   "non_cubic_fp32": (non_cubic(I.ne_atom()), dict(precision=1)),
                   "omega0.8_3orb": (I.atom(6, 18, h=0.3, seed=12), dict(omega=0.8))}[case]
     s, o = make_pair(L, system, **kw)
-    s.set_variant(12)
+    s.set_variant(variant)
     s.relax(25)
     for _ in range(25):
         o.step()
