@@ -178,10 +178,13 @@ def h2o_batch_run(count, check_every, max_steps):
                             stop_checks=FP32_RULE["stop_checks"]) for sy in systems]
     # update-kernel variant per grid size: timed on the first member of each size,
     # the others take the cached choice (outside the timed region)
-    variants = {}
+    variants, tuned_us = {}, {}
     for sy, m in zip(systems, members):
-        v, _ = m.autotune(reps=3)
-        variants.setdefault(f"{sy.dims[0]}^3", v)
+        v, ms = m.autotune(reps=3)
+        key = f"{sy.dims[0]}^3"
+        if key not in variants:
+            variants[key] = v
+            tuned_us[key] = None if ms is None else [None if x is None else round(1e3 * x, 1) for x in ms]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st, steps = b.relax(max_steps, dE_tol, check_every)
@@ -203,6 +206,7 @@ def h2o_batch_run(count, check_every, max_steps):
             "wall_s": wall, "h2o_solves_per_s": count / wall, "orbital_site_updates_per_s": upd / wall,
             "steps_min": min(steps), "steps_max": max(steps), "nodes_total": sum(sy.n_sites for sy in systems),
             "update_variants": variants,
+            "update_variant_us": tuned_us,    # per-launch time of every variant timed, per grid size
             "e_total_first4": e,
             "dE_vs_oracle_Ha": {str(k): v for k, v in dE.items()},
             "max_abs_dE_vs_oracle_Ha": max((abs(v) for v in dE.values()), default=None)}
@@ -414,7 +418,8 @@ def main():
         avg_s = k1_ms / k1_n * 1e-3
         alg = k1_bytes_per_launch(system.n_orb, system.n_sites, s_bytes, scheme, ortho == lbks.LBKS_ORTHO_W)
         ach = alg / avg_s / 1e9
-        tkey = f"{args.workload}_{args.precision}_" + (f"v{variant}" if scheme == 0 else "collapsed" if bricks else "")
+        tkey = f"{args.workload}_{args.precision}_" + (f"v{variant}" if scheme == 0
+                                                       else f"collapsed_v{variant}" if bricks else "")
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(tkey) if tkey else None,
                            "kernel": ("k_stream_collide_wide" if variant is not None and variant & 8 and system.n_orb <= 5
