@@ -459,6 +459,17 @@ int read_energies(lbks_ctx *c, lbks_energies *out, double *errflag)
     return 0;
 }
 
+// Update-kernel variant before any autotuning (measured on MI355X at the 96^3-128^3
+// workloads): the population update of at most five orbitals takes the rolled wide
+// form in dispatch order, the brick update depth 8 (FP64) or 12 (FP32) with the
+// XCD remap, the node-per-lane kernels their per-precision default.
+int initial_variant(int precision, bool populations, int no, bool wmode)
+{
+    if (no <= 5 && populations) return 13;
+    if (no <= 5 && !wmode) return precision ? 1 : 0;
+    return default_variant(precision);
+}
+
 int read_scalar(lbks_ctx *c, int idx, double *v)
 {
     HIPCHK(c, hipMemcpyAsync(v, c->h.scal + idx, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -613,7 +624,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     for (int k = 0; k < 4; ++k) pl.nbrick[k] = bricks_of(h.nx, h.ny, h.nz, brick_depth(k));
     pl.brick_partials = brick_partials(h.ntile, h.ntile_brick);
     pl.n_inst = 1;
-    pl.variant = default_variant(pl.precision);
+    pl.variant = initial_variant(pl.precision, p->scheme == LBKS_SCHEME_POPULATIONS, pl.no, pl.wmode);
 
     int rc = 0;
     auto bail = [&](int code) {
