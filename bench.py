@@ -286,6 +286,80 @@ def serve_run(n_requests, rate, check_every, budget_gb, grids):
     return out
 
 
+def cd_run(n_steps, h=0.01, restart_every=500):
+    """Concurrent dynamics (complex orbitals in real time) on the Ne 96^3 FP64
+    workload, nucleus fixed: the orbitals are relaxed to the ground state (|dE| <
+    1e-9 Ha per 100 steps), then `n_steps` time-centred steps of h a.u. (a restart
+    every `restart_every`) are timed (wall and the step kernel's HIP events; a
+    restart counts as one launch).  Algorithmic bytes of one step-kernel launch:
+    per orbital-site 48 B (psi^n at the node, psi^(n-1) in, psi^(n+1) out, complex
+    FP64), per site 8 B (V)."""
+    import torch
+    from paper_1507_07666_amd import lbks
+    sy = workload("ne96")
+    s = lbks.Solver.for_system(sy)
+    _, relax_steps = s.relax(8000, 1e-9, 100)
+    s.cd_start(h, restart_every)
+    e0 = s.cd_energy()["e_total"]
+    s.cd_step(20)                           # warm-up
+    torch.cuda.synchronize()
+    s.set_timing(True)
+    t0 = time.perf_counter()
+    s.cd_step(n_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, k = s.kernel_time(1)
+    e1 = s.cd_energy()["e_total"]
+    s.cd_stop()
+    s.close()
+    alg = sy.n_sites * (sy.n_orb * 48 + 8)
+    avg_s = ms / max(k, 1) * 1e-3
+    return {"metric": "concurrent-dynamics steps/s", "value": n_steps / wall, "unit": "steps/s",
+            "ms_per_step": 1e3 * wall / n_steps, "orbital_site_updates_per_s": sy.n_orb * sy.n_sites * n_steps / wall,
+            "roofline": {"bound": "hbm", "kernel": "k_cd_step", "avg_us": avg_s * 1e6, "launches": k,
+                         "alg_bytes_per_launch": alg, "achieved": alg / avg_s / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": alg / avg_s / 1e9 / HBM_PEAK_GBS},
+            "e_total_drift_Ha": e1 - e0, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"Ne atom 96^3 at 0.2 bohr, 5 orbitals, FP64, nucleus fixed, relaxed {relax_steps} "
+                                   f"steps to the ground state, then time step {h} a.u. ({h / 41.341373335 * 1e3:.3f} as), "
+                                   f"a restart every {restart_every} steps"}}
+
+
+def sequential_run(dE_tol=1e-9, check_every=50):
+    """The sequential Gram-Schmidt order against the concurrent one on the same
+    Be atom (32^3 at 0.3 bohr, 2 orbitals, FP64, omega = 1 field update), both from
+    the same seeded start to the same tolerances: lattice steps, wall time, and the
+    difference of the converged total energies."""
+    import torch
+    from paper_1507_07666_amd import inputs as I
+    from paper_1507_07666_amd import lbks
+    sy = I.atom(4, 32, h=0.3, softening=0.3, seed=4)
+    out = {"workload": "Be atom 32^3 at 0.3 bohr, softening 0.3, 2 orbitals, FP64, omega = 1 field update, "
+                       f"|dE| < {dE_tol:g} Ha (and |d eps_k| < {dE_tol:g} Ha per stage) checked every {check_every} steps"}
+    res = {}
+    for order in ("concurrent", "sequential"):
+        s = lbks.Solver(lbks.params_for(sy, init=lbks.LBKS_INIT_USER, scheme=lbks.LBKS_SCHEME_COLLAPSED))
+        s.set_nuclei(sy.Z, sy.R)
+        s.set_orbitals(sy.psi0())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if order == "concurrent":
+            rc, steps = s.relax(200000, dE_tol, check_every)
+            sweeps = None
+        else:
+            rc, steps, sweeps = s.relax_sequential(200000, dE_tol, dE_tol, check_every, 50)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e = s.energy()
+        s.close()
+        res[order] = {"status": rc, "steps": steps, "sweeps": sweeps, "wall_s": wall, "e_total": e["e_total"],
+                      "eps": [float(x) for x in e["eps"][:sy.n_orb]]}
+    out.update(res)
+    out["dE_sequential_minus_concurrent_Ha"] = res["sequential"]["e_total"] - res["concurrent"]["e_total"]
+    out["steps_ratio"] = res["sequential"]["steps"] / max(1, res["concurrent"]["steps"])
+    return out
+
+
 def serve_sweep(n_requests, check_every, budget_gb, grids, factors=(0.25, 0.5, 1.0, 2.0)):
     """Saturation rate first (every request arrives at t = 0: requests/s of the
     drained queue), then Poisson arrivals of the same seeded stream at the given
@@ -318,6 +392,8 @@ def main():
     ap.add_argument("--ortho", default="gs", choices=["gs", "w"],
                     help="Cholesky Gram-Schmidt, or the paper's orthogonalisation source")
     ap.add_argument("--check-every", type=int, default=100)
+    ap.add_argument("--hermite", type=int, default=2, choices=[2, 4],
+                    help="order of the equilibrium and source weights")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
@@ -356,6 +432,12 @@ def main():
     if args.workload == "bo_md":
         print(json.dumps(bo_md_run(max(2, args.steps // 15))), flush=True)
         return
+    if args.workload == "cd":
+        print(json.dumps(cd_run(args.steps)), flush=True)
+        return
+    if args.workload == "sequential":
+        print(json.dumps(sequential_run()), flush=True)
+        return
     if args.workload == "serve_sweep":
         print(json.dumps(serve_sweep(args.requests, 100, args.budget_gb, I_SERVE_GRIDS)), flush=True)
         return
@@ -363,7 +445,8 @@ def main():
     prec = lbks.LBKS_FP64 if args.precision == "fp64" else lbks.LBKS_FP32_BULK
     scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED
     ortho = lbks.LBKS_ORTHO_GS if args.ortho == "gs" else lbks.LBKS_ORTHO_W
-    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega, ortho=ortho)
+    solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega, ortho=ortho,
+                                    hermite=args.hermite)
     s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
 
     if args.variant is not None:
@@ -407,6 +490,7 @@ def main():
                                f"softening {system.softening}, {system.n_orb} orbitals, "
                                f"{args.precision} {args.scheme}, seed {system.seed}"
                                + (f", omega {args.omega}" if args.omega != 1.0 else "")
+                               + (", fourth-order weights" if args.hermite == 4 else "")
                                + (", orthogonalisation source W" if args.ortho == "w" else ""),
                    "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
                    "omega": args.omega,

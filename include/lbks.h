@@ -366,10 +366,12 @@ size_t lbks_device_bytes(const lbks_ctx *ctx);
  * invalid). */
 size_t lbks_estimate_bytes(const lbks_params *p);
 
-/* Kernel timing: when enabled, every launch of the stream-collide kernel is
- * bracketed by HIP events on the context's stream.  lbks_kernel_time returns
- * the summed duration (ms) and the launch count since the last reset, and
- * synchronises the stream.  kernel: 0 = stream-collide. */
+/* Kernel timing: when enabled, every launch of the update kernel (the population
+ * stream-collide or the omega = 1 field update) and of the concurrent-dynamics
+ * step is bracketed by HIP events on the context's stream.  lbks_kernel_time
+ * returns the summed duration (ms) and the launch count since the last reset,
+ * and synchronises the stream.  kernel: 0 = update kernel, 1 = concurrent-
+ * dynamics step (lbks_cd_step; a restart step counts as one launch). */
 int lbks_set_timing(lbks_ctx *ctx, int32_t enable);
 int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 

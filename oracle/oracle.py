@@ -632,8 +632,8 @@ class ConcurrentDynamics:
         H being the operator whose steady state the relaxation reaches (its
         Rayleigh quotients are the eps_j), with the potential and orthogonality
         sources turned by i as printed;
-      * U_jp = kappa w_p q_p E_j phi_j, "in charge of keeping the energy at E_j",
-        is read as each orbital's energy reference: orbital j is advanced with
+      * U_jp = kappa w_p q_p E_j phi_j, the source that holds the orbital's
+        energy at E_j, is read as each orbital's energy reference: orbital j is advanced with
         H - E_j, E_j its Rayleigh quotient at the start.  That is a global phase
         e^{i E_j t} per orbital (densities, energies and forces are unchanged) which
         makes the ground state stationary; without it the density picks up the

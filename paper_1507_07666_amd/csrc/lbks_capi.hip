@@ -55,12 +55,13 @@ struct lbks_ctx {
     int passes = 0;             // consecutive passing checks
     double *d_zr = nullptr;     // nuclei table [4 * LBKS_MAX_NUC + 1]
     std::string err;
-    // timing of the stream-collide kernel
+    // timing of the update kernel (kind 0) and of the concurrent-dynamics step (kind 1)
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    std::vector<int> ev_kind;    // the kind of each pair
     size_t ev_used = 0;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
+    double timed_ms[2] = {0.0, 0.0};
+    int64_t timed_launches[2] = {0, 0};
     lbks_batch *batch = nullptr;
     // concurrent dynamics (lbks_cd_*): complex orbitals at two time levels plus two
     // work levels, [4][n_orb][site] of double2
@@ -401,27 +402,37 @@ int flush_timing(lbks_ctx *c)
     for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
         float ms = 0.f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
-        c->timed_ms += ms;
-        c->timed_launches += 1;
+        const int k = c->ev_kind[i / 2];
+        c->timed_ms[k] += ms;
+        c->timed_launches[k] += 1;
     }
     c->ev_used = 0;
+    c->ev_kind.clear();
     return 0;
 }
 
 // One lattice step: orthonormalise, density, Hartree sweeps, potential, then the
 // lattice Boltzmann update of every orbital (populations or collapsed form).
+// Start a timed launch of `kind`: records the start event on the context's stream
+// and returns the stop event to record after the launch.
+int timing_begin(lbks_ctx *c, int kind, hipEvent_t *stop)
+{
+    int rc;
+    if (c->ev_used + 2 > 4096 && (rc = flush_timing(c))) return rc;
+    hipEvent_t e0 = next_event(c), e1 = next_event(c);
+    if (!e0 || !e1) return fail(c, LBKS_E_HIP, "hipEventCreate failed");
+    c->ev_kind.push_back(kind);
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    *stop = e1;
+    return 0;
+}
+
 int enqueue_step(lbks_ctx *c)
 {
     int rc;
     KCHK(c, plan_pre_update(c->plan, c->p.hartree, c->p.poisson_sweeps, c->stream));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-        if (c->ev_used + 2 > 4096 && (rc = flush_timing(c))) return rc;
-        e0 = next_event(c);
-        e1 = next_event(c);
-        if (!e0 || !e1) return fail(c, LBKS_E_HIP, "hipEventCreate failed");
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-    }
+    hipEvent_t e1 = nullptr;
+    if (c->timing && (rc = timing_begin(c, 0, &e1))) return rc;
     KCHK(c, plan_update(c->plan, c->p.scheme, c->parity, c->stream));
     if (c->p.scheme == LBKS_SCHEME_POPULATIONS) c->parity ^= 1;
     if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
@@ -1123,12 +1134,15 @@ extern "C" int lbks_cd_step(lbks_ctx *c, int64_t steps)
     int rc;
     for (int64_t k = 0; k < steps; ++k) {
         if ((rc = cd_potential(c))) return rc;
+        hipEvent_t stop = nullptr;
+        if (c->timing && (rc = timing_begin(c, 1, &stop))) return rc;
         if (c->cd_restart > 0 && (c->cd_steps + 1) % c->cd_restart == 0) {
             if ((rc = cd_restart_step(c))) return rc;
         } else {
             KCHK(c, launch_cd_step(c->plan, cd_level(c, c->cd_cur), cd_level(c, 1 - c->cd_cur), c->cd_h, c->cd_ref,
                                    c->stream));
         }
+        if (stop) HIPCHK(c, hipEventRecord(stop, c->stream));
         c->cd_cur = 1 - c->cd_cur;
         c->cd_steps += 1;
     }
@@ -1229,18 +1243,20 @@ extern "C" int lbks_set_timing(lbks_ctx *c, int32_t enable)
     int rc = flush_timing(c);
     if (rc) return rc;
     c->timing = enable != 0;
-    c->timed_ms = 0.0;
-    c->timed_launches = 0;
+    for (int k = 0; k < 2; ++k) {
+        c->timed_ms[k] = 0.0;
+        c->timed_launches[k] = 0;
+    }
     return 0;
 }
 
 extern "C" int lbks_kernel_time(lbks_ctx *c, int32_t kernel, double *total_ms, int64_t *launches)
 {
-    if (!c || kernel != 0) return LBKS_E_INVAL;
+    if (!c || kernel < 0 || kernel > 1) return LBKS_E_INVAL;
     int rc = flush_timing(c);
     if (rc) return rc;
-    if (total_ms) *total_ms = c->timed_ms;
-    if (launches) *launches = c->timed_launches;
+    if (total_ms) *total_ms = c->timed_ms[kernel];
+    if (launches) *launches = c->timed_launches[kernel];
     return 0;
 }
 

@@ -7,12 +7,15 @@
 //   psi_j^{n+1} = psi_j^{n-1} - 2 i h (H - E_j) psi_j^n,  H u = K_h u + S_chi(V u),
 //   K_h u = -(S_xi u - u) / (D dx^2),
 // H being the operator whose steady state the relaxation reaches and E_j the
-// orbital's energy at the start (the source U_jp, "keeping the energy at E_j",
-// read as each orbital's energy reference: a global phase per orbital that
-// leaves densities and forces unchanged and keeps the two-step scheme's
-// parasitic mode from growing through V).  W = 0 (the evolution keeps the
-// orbitals orthonormal up to its own error).  Orbitals are
-// FP64 complex, interleaved (re, im) per node: [orbital][site] of double2.
+// orbital's energy at the last (re)start (the source U_jp, which holds the
+// orbital's energy at E_j, read as each orbital's energy reference: a global
+// phase per orbital that leaves densities and forces unchanged and keeps the
+// two-step scheme's parasitic mode from growing through V; restarts re-centre
+// E_j as the nuclei move).  W = 0 (the evolution keeps the orbitals orthonormal
+// up to its own error).  Orbitals are
+// FP64 complex, interleaved (re, im) per node: [orbital][site] of double2.  Every
+// kernel gives each XCD one contiguous range of tiles, so its L2 holds the
+// neighbour planes of the 19-point reads.
 #include <type_traits>
 
 #include "lbks_device.h"
@@ -106,7 +109,8 @@ __global__ __launch_bounds__(BS) void k_cd_apply(const InstDesc *__restrict__ de
                                                  double2 *__restrict__ out, CdRef ref)
 {
     const InstDesc &d = descs[0];
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);   // each XCD walks one contiguous tile range
+    const int s = tile * BS + threadIdx.x;
     if (s >= d.nsite) return;
     const int n = orbitals<NO>(d);
     const int x = s % d.nx, yz = s / d.nx, y = yz % d.ny, z = yz / d.ny;
@@ -128,7 +132,8 @@ __global__ __launch_bounds__(BS) void k_cd_taylor(const InstDesc *__restrict__ d
 {
     const InstDesc &d = descs[0];
     const int n = orbitals<NO>(d);
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);   // each XCD walks one contiguous tile range
+    const int s = tile * BS + threadIdx.x;
     double m[NMOM];
 #pragma unroll
     for (int q = 0; q < NMOM; ++q) m[q] = 0.0;
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(BS) void k_cd_taylor(const InstDesc *__restrict__ d
         const int x = s % d.nx, yz = s / d.nx, y = yz % d.ny, z = yz / d.ny;
         density_moments<NO>(d, w, s, x, y, z, m);
     }
-    block_sum_store(m, NMOM, d.m_part + blockIdx.x, d.ntile);
+    block_sum_store(m, NMOM, d.m_part + tile, d.ntile);
 }
 
 // prev <- prev - 2 i h (H - E_j) cur (the new time level overwrites the oldest), with the
@@ -160,7 +165,8 @@ __global__ __launch_bounds__(BS) void k_cd_step(const InstDesc *__restrict__ des
 {
     const InstDesc &d = descs[0];
     const int n = orbitals<NO>(d);
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);   // each XCD walks one contiguous tile range
+    const int s = tile * BS + threadIdx.x;
     double m[NMOM];
 #pragma unroll
     for (int q = 0; q < NMOM; ++q) m[q] = 0.0;
@@ -182,7 +188,7 @@ __global__ __launch_bounds__(BS) void k_cd_step(const InstDesc *__restrict__ des
         }
         density_moments<NO>(d, w, s, x, y, z, m);
     }
-    block_sum_store(m, NMOM, d.m_part + blockIdx.x, d.ntile);
+    block_sum_store(m, NMOM, d.m_part + tile, d.ntile);
 }
 
 // Per-node energy terms of the complex orbitals, laid out as k_energy_terms lays
@@ -195,7 +201,8 @@ __global__ __launch_bounds__(BS) void k_cd_energy_terms(const InstDesc *__restri
 {
     const InstDesc &d = descs[0];
     const int n = orbitals<NO>(d);
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);   // each XCD walks one contiguous tile range
+    const int s = tile * BS + threadIdx.x;
     double v[2 * NO + NEBASE];
 #pragma unroll
     for (int q = 0; q < 2 * NO + NEBASE; ++q) v[q] = 0.0;
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(BS) void k_cd_energy_terms(const InstDesc *__restri
         v[2 * NO + 3] = rho * ec;
         v[2 * NO + 4] = rho;
     }
-    block_sum_store(v, 2 * NO + NEBASE, d.e_part + blockIdx.x, d.ntile);
+    block_sum_store(v, 2 * NO + NEBASE, d.e_part + tile, d.ntile);
 }
 
 // prev = (psi_hat, 0): the real orthonormal orbitals as the first time level.
@@ -259,7 +266,8 @@ __global__ __launch_bounds__(BS) void k_cd_init(const InstDesc *__restrict__ des
 {
     const InstDesc &d = descs[0];
     const int n = orbitals<NO>(d);
-    const int s = blockIdx.x * BS + threadIdx.x;
+    const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);   // each XCD walks one contiguous tile range
+    const int s = tile * BS + threadIdx.x;
     if (s >= d.nsite) return;
     const size_t N = (size_t)d.nsite;
     const double *ph = (const double *)d.psihat;

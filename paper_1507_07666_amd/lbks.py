@@ -392,10 +392,12 @@ class Solver:
             return ch.value, None                     # the process cache answered
         return ch.value, [None if t < 0 else t for t in times]
 
-    def kernel_time(self):
+    def kernel_time(self, kernel=0):
+        """(summed ms, launches) of the timed launches: kernel 0 = the update kernel,
+        1 = the concurrent-dynamics step."""
         ms = c_double()
         n = c_int64()
-        _check(self.ctx, load().lbks_kernel_time(self.ctx, 0, ctypes.byref(ms), ctypes.byref(n)))
+        _check(self.ctx, load().lbks_kernel_time(self.ctx, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
     def close(self):
