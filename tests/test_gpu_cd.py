@@ -132,7 +132,12 @@ def test_cd_state_rules_and_stability_check(L):
         with pytest.raises(L.LbksError) as ex:
             call()
         assert ex.value.code == L.LBKS_E_STATE
+    s.set_timing(True)
     s.cd_step(3)
+    ms, launches = s.kernel_time(1)                    # the CD step kernel, timed per launch
+    assert launches == 3 and ms > 0.0
+    assert s.kernel_time(0) == (0.0, 0)                # no update-kernel launch in the dynamics
+    s.set_timing(False)
     e = s.cd_energy()
     assert e["steps"] == 3 and np.isfinite(e["e_total"])
     s.cd_stop()
