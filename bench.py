@@ -37,6 +37,9 @@ def workload(name):
         return I.he_atom()
     if name == "ch4":
         return I.ch4()
+    if name.startswith("he") and name[2:].isdigit():     # He on n^3 nodes at 0.3 * 32 / n bohr
+        n = int(name[2:])
+        return I.he_atom().scaled(n, h=0.3 * 32 / n)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -394,6 +397,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=100)
     ap.add_argument("--hermite", type=int, default=2, choices=[2, 4],
                     help="order of the equilibrium and source weights")
+    ap.add_argument("--fold", type=int, default=0, choices=[0, -1],
+                    help="-1: the overlap and multipole totals always by their own reduction kernels")
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip the per-kernel HIP events")
@@ -446,7 +451,7 @@ def main():
     scheme = lbks.LBKS_SCHEME_POPULATIONS if args.scheme == "populations" else lbks.LBKS_SCHEME_COLLAPSED
     ortho = lbks.LBKS_ORTHO_GS if args.ortho == "gs" else lbks.LBKS_ORTHO_W
     solver = lbks.Solver.for_system(system, precision=prec, scheme=scheme, omega=args.omega, ortho=ortho,
-                                    hermite=args.hermite)
+                                    hermite=args.hermite, fold=args.fold)
     s_bytes = 8 if prec == lbks.LBKS_FP64 else 4
 
     if args.variant is not None:
@@ -470,6 +475,7 @@ def main():
     elapsed = time.perf_counter() - t0
     k1_ms, k1_n = solver.kernel_time() if not args.no_timing else (0.0, 0)
     e = solver.energy()
+    fold_bits = solver.fold()
     solver.close()
 
     value = system.n_orb * system.n_sites * steps / elapsed
@@ -493,7 +499,7 @@ def main():
                                + (", fourth-order weights" if args.hermite == 4 else "")
                                + (", orthogonalisation source W" if args.ortho == "w" else ""),
                    "n_orb": system.n_orb, "nodes": system.n_sites, "check_every": args.check_every,
-                   "omega": args.omega,
+                   "omega": args.omega, "fold": fold_bits,
                    "update_variant": variant, "autotune_ms": tune_ms,
                    "parallelism": "single GPU"},
         "e_total": e["e_total"],

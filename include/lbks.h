@@ -114,7 +114,13 @@ typedef struct lbks_params {
     double deps_tol;         /* > 0: a check also needs |change of sum_j eps_j| < deps_tol */
     int32_t hermite;         /* order of the Hermite expansion of the equilibrium and source
                                 weights: 2 (0 means 2) or 4 (see LBKS_HERMITE_4) */
-    int32_t reserved[3];     /* must be zero */
+    int32_t fold;            /* 0 (default): on grids of at most 65536 nodes (256 tiles of 256) the
+                                overlap totals (at most five orbitals) and the multipole totals are
+                                summed by every workgroup of the kernel that uses them, in the order
+                                of the separate reduction kernel: two launches fewer per lattice
+                                step, the same results bit for bit; -1: always by the separate
+                                kernels */
+    int32_t reserved[2];     /* must be zero */
 } lbks_params;
 
 /* Fourth-order Hermite weights (params.hermite = 4; the paper uses fourth order
@@ -396,6 +402,11 @@ int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *l
  * (FP32).  lbks_set_variant: LBKS_E_INVAL outside 0..15. */
 int lbks_set_variant(lbks_ctx *ctx, int32_t variant);
 int lbks_get_variant(const lbks_ctx *ctx);
+
+/* Which totals this context's kernels sum themselves (params.fold): bit 0 the
+ * overlap, bit 1 the multipoles; 0 when neither is folded or params.fold = -1;
+ * LBKS_E_INVAL for a NULL context. */
+int lbks_get_fold(const lbks_ctx *ctx);
 
 /* Time every distinct update-kernel variant `reps` times on the context's
  * current state and keep the fastest (state unchanged).  Choices are cached per

@@ -212,7 +212,8 @@ int validate(const lbks_params *p, std::string &why)
     }
     if (p->stop_checks < 0 || p->stop_checks > 1000) { why = "stop_checks must be in [0, 1000]"; return LBKS_E_INVAL; }
     if (!(p->deps_tol >= 0.0) || !isfinite(p->deps_tol)) { why = "deps_tol must be finite and >= 0"; return LBKS_E_INVAL; }
-    for (int i = 0; i < 3; ++i)
+    if (p->fold != 0 && p->fold != -1) { why = "fold must be 0 or -1"; return LBKS_E_INVAL; }
+    for (int i = 0; i < 2; ++i)
         if (p->reserved[i]) { why = "reserved fields must be zero"; return LBKS_E_INVAL; }
     return 0;
 }
@@ -589,6 +590,7 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     }
     h.rho_floor = p->rho_floor;
     h.active = ~0u;
+    h.fold = fold_bits(h.ntile, h.n_orb, p->fold == 0);
     h.e_nn = 0.0;
     for (int j = 0; j < MAXO; ++j) h.occ[j] = 0.0;
     if (p->xc == LBKS_XC_B88_LYP_POLARISED) {
@@ -634,6 +636,8 @@ extern "C" int lbks_create(const lbks_params *p, const lbks_device *dev, lbks_ct
     pl.ntile_brick = h.ntile_brick;
     for (int k = 0; k < 4; ++k) pl.nbrick[k] = bricks_of(h.nx, h.ny, h.nz, brick_depth(k));
     pl.brick_partials = brick_partials(h.ntile, h.ntile_brick);
+    pl.fold_s = (h.fold & FOLD_S) != 0;
+    pl.fold_m = (h.fold & FOLD_M) != 0;
     pl.n_inst = 1;
     pl.variant = initial_variant(pl.precision, p->scheme == LBKS_SCHEME_POPULATIONS, pl.no, pl.wmode);
 
@@ -1280,6 +1284,11 @@ extern "C" int lbks_get_variant(const lbks_ctx *c)
     return c ? c->plan.variant : LBKS_E_INVAL;
 }
 
+extern "C" int lbks_get_fold(const lbks_ctx *c)
+{
+    return c ? c->h.fold : LBKS_E_INVAL;
+}
+
 namespace {
 
 struct TuneKey {
@@ -1528,7 +1537,7 @@ int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
         int2 *tw = (int2 *)(host.data() + o.site_w);
         const int kw = wide_nodes(g.precision ? 4 : 8);
         int ns = 0, ng = 0, nr = 0, nb = 0, nw = 0;
-        bool all_brick = true;
+        bool all_brick = true, all_fold_s = true, all_fold_m = true;
         for (size_t q = 0; q < g.members.size(); ++q) {
             const lbks_ctx *c = b->members[g.members[q]];
             InstDesc d = c->h;
@@ -1540,6 +1549,8 @@ int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
             for (int t = 0; t < bricks_of(d.nx, d.ny, d.nz, brick_depth(g.variant)); ++t) tb[nb++] = make_int2((int)q, t);
             for (int t = 0; t < (d.ntile + kw - 1) / kw; ++t) tw[nw++] = make_int2((int)q, t);
             all_brick = all_brick && brick_partials(d.ntile, d.ntile_brick);
+            all_fold_s = all_fold_s && (d.fold & FOLD_S);
+            all_fold_m = all_fold_m && (d.fold & FOLD_M);
             ti[q] = (int)q;
         }
         Plan &pl = g.plan;
@@ -1558,6 +1569,8 @@ int batch_build(lbks_batch *b, void *fixed = nullptr, size_t fixed_cap = 0)
         pl.tt.site_w = (const int2 *)(base + o.site_w);
         pl.tt.n_site_w = o.n_site_w;
         pl.brick_partials = all_brick;
+        pl.fold_s = all_fold_s;
+        pl.fold_m = all_fold_m;
         pl.precision = g.precision;
         pl.no = g.no;
         pl.wmode = g.wmode;

@@ -229,6 +229,55 @@ static __device__ bool reduce_columns(const double *__restrict__ part, int ntile
     return true;
 }
 
+// The totals of reduce_columns, bit for bit, summed by one workgroup alone, for
+// an instance whose first-level groups hold at most L tiles (L <= 64, ntile <= RG
+// L) and nq RG <= BS.  In reduce_columns a group then sits in the first wave
+// alone: lane l holds 0 + part[t0 + l] (zero past the group), the wave adds its
+// lanes pairwise over lane bit 5, then 4, ..., 0 (wave_reduce_scatter), and the
+// zero sums of the other waves leave the group sum unchanged (x + 0 = x for every
+// x but -0, which 0 + part never is).  Here thread (c, g) forms group g of column c
+// by the same pairwise tree (pairs past lane L - 1 add zeros and are skipped),
+// then thread c adds the RG group sums in the order g = 0, 1, ..., as the last
+// workgroup of reduce_columns does.  Totals land in `out` (LDS; grp is LDS
+// scratch of RG nq doubles); every thread of the workgroup must call this.
+template <int L>
+__device__ void fold_columns_l(const double *__restrict__ part, int ntile, int nq, double *grp, double *out)
+{
+    static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "L must be a power of two <= 64");
+    const int t = threadIdx.x;
+    if (t < nq * RG) {
+        const int c = t / RG, g = t % RG;
+        const int t0 = (int)((long long)ntile * g / RG), t1 = (int)((long long)ntile * (g + 1) / RG);
+        const auto *col = gmem(part) + (size_t)c * ntile + t0;
+        double a[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) a[l] = t0 + l < t1 ? 0.0 + col[l] : 0.0;
+#pragma unroll
+        for (int b = L / 2; b >= 1; b >>= 1)
+#pragma unroll
+            for (int m = 0; m < b; ++m) a[m] += a[m + b];
+        grp[c * RG + g] = 0.0 + a[0];
+    }
+    __syncthreads();
+    if (t < nq) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < RG; ++k) s += grp[t * RG + k];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+// fold_columns_l with the smaller tree (8 or 16 tiles) that holds the longest
+// group, ceil(ntile / RG) <= 16 tiles: a larger tree only adds zeros, so either
+// gives the same totals, and the smaller one issues fewer loads.
+__device__ __forceinline__ void fold_columns(const double *__restrict__ part, int ntile, int nq, double *out)
+{
+    __shared__ double grp[RG * RG];     // [column][group]: nq RG <= BS gives nq <= BS / RG = RG
+    if ((ntile + RG - 1) / RG <= 8) fold_columns_l<8>(part, ntile, nq, grp, out);
+    else fold_columns_l<16>(part, ntile, nq, grp, out);
+}
+
 __device__ __forceinline__ double node_coord(int i, int n, double h)
 {
     return ((double)i - 0.5 * (double)(n - 1)) * h;

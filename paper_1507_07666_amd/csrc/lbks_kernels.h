@@ -44,6 +44,21 @@ constexpr int RG = 16;         // first-level workgroups per instance of the fin
 // Columns of a partial array padded to a whole number of chunks.
 __host__ __device__ constexpr int padded_cols(int nq) { return (nq + RCH - 1) / RCH * RCH; }
 
+// Small instances skip the two finalize kernels whose totals one kernel needs
+// next: every workgroup of that kernel sums the tile partials itself, in the
+// finalize kernel's order of additions, so the results are the same bit for bit.
+// The overlap S goes to the orthonormalisation (up to five orbitals), the
+// multipoles to the ghost-face kernel, for instances of at most RG * FOLD_GROUP
+// tiles (measured on MI355X: 48.5 -> 39.2 us per step at 32^3; with 432 or 1024
+// tiles the multipole fold alone no longer pays).  InstDesc::fold holds the bits.
+constexpr int FOLD_S = 1, FOLD_M = 2;
+constexpr int FOLD_GROUP = 16;   // tiles per first-level group, at most
+inline int fold_bits(int ntile, int n_orb, bool enabled)
+{
+    if (!enabled || ntile > RG * FOLD_GROUP) return 0;
+    return (n_orb <= 5 ? FOLD_S : 0) | FOLD_M;
+}
+
 // Offsets into the per-instance FP64 scalar block.
 constexpr int SC_MOM = 0;                  // 10 multipoles
 constexpr int SC_S = 16;                   // packed lower overlap, 136 values
@@ -66,6 +81,7 @@ struct InstDesc {
     int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
     unsigned active;           // orbitals that take the omega = 1 field update (bit j); the others keep
                                // their fields (the sequential Gram-Schmidt order); all ones otherwise
+    int fold;                  // FOLD_S / FOLD_M: the overlap / multipole totals are summed by their consumer
     double h, h3, omega, dt, D, omega_sor, rho_floor, e_nn;
     double occ[MAXO];
     double xi[Q], chi[Q];
@@ -121,6 +137,7 @@ struct Plan {
                           // over the directions, bit 1 is unused);
                           // the brick update reads bits 0 and 1 as its depth and bit 2 as its order
     bool brick_partials = true;   // every instance gets its overlap partials from the brick update
+    bool fold_s = false, fold_m = false;   // every instance folds the overlap / multipole finalize
 };
 
 // Default update-kernel variant per precision (measured on MI355X): FP64 keeps the

@@ -140,36 +140,25 @@ __global__ __launch_bounds__(BS) void k_overlap_psi(const InstDesc *__restrict__
 
 // ---------------------------------------------------------- overlap / GS
 
-// S from the tile partials (fixed order), then C.  GS: S = L L^T, C = L^{-T}
-// (psi_hat_j = sum_{l<=j} psi_l C_lj, classical Gram-Schmidt order).  W:
-// n_j = sqrt(S_jj), C = diag(1/n), C*_lj = -Lambda_jl / n_l (l < j), C*_jj = 1/n_j
-// with Lambda_jl = S_jl / (n_j n_l), i.e. psi*_j = psi_hat_j - sum_{l<j} Lambda_jl psi_hat_l.
-__global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restrict__ descs,
-                                                         const int *__restrict__ list)
+// The coefficients of the orthonormalisation from the overlap S (packed lower,
+// h^3 included), by the first wave; every thread of the workgroup calls it.  GS:
+// S = L L^T, C = L^{-T} (psi_hat_j = sum_{l<=j} psi_l C_lj, classical Gram-Schmidt
+// order).  W: n_j = sqrt(S_jj), C = diag(1/n), C*_lj = -Lambda_jl / n_l (l < j),
+// C*_jj = 1/n_j with Lambda_jl = S_jl / (n_j n_l), i.e. psi*_j = psi_hat_j -
+// sum_{l<j} Lambda_jl psi_hat_l.  Writes C[l ld + j] (GS: l <= j < n; W: the
+// diagonal) and C*[l ld + j] (W: l <= j < n) and nothing else; n <= M.  Returns
+// true on the lanes of the first wave that found S not positive definite.
+template <int M>
+__device__ bool ortho_coefficients(const double *S, int n, int ortho, double *C, double *Cs, int ld)
 {
-    const GroupRef gr = resolve_group(list);
-    const InstDesc &d = descs[gr.inst];
-    const int n = d.n_orb, np = npair_of(n);
-    __shared__ double S[MAXO * (MAXO + 1) / 2];
-    __shared__ double L[MAXO][MAXO + 1];
-    __shared__ double Li[MAXO][MAXO + 1];
-    if (!reduce_columns(d.s_part, d.ntile, np, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, S)) return;
-    // the first wave finishes: lane i owns row i of L, lane c column c of L^{-1}
+    __shared__ double L[M][M + 1];
+    __shared__ double Li[M][M + 1];
+    // lane i owns row i of L, lane c column c of L^{-1}
     const int lane = threadIdx.x;
     const bool w0 = threadIdx.x < 64;
-    double *C = d.C;
-    double *Cs = d.C + MAXO * MAXO;
     bool bad = false;
-    if (w0)
-        for (int q = lane; q < np; q += 64) {
-            S[q] *= d.h3;
-            d.scal[SC_S + q] = S[q];
-            if (!isfinite(S[q])) bad = true;
-        }
-    __syncthreads();
     auto Sget = [&](int i, int j) { return i >= j ? S[i * (i + 1) / 2 + j] : S[j * (j + 1) / 2 + i]; };
-    // entries outside the n x n block stay zero from creation
-    if (d.ortho == 0) {
+    if (ortho == 0) {
         // Cholesky S = L L^T by columns: L_jj = sqrt(S_jj - sum_k<j L_jk^2),
         // L_ij = (S_ij - sum_k<j L_ik L_jk) / L_jj for i > j
         for (int j = 0; j < n; ++j) {
@@ -196,27 +185,56 @@ __global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restr
                 for (int k = c; k < i; ++k) sum -= L[i][k] * Li[k][c];
                 Li[i][c] = sum / L[i][i];
             }
-            for (int j = c; j < n; ++j) C[c * MAXO + j] = Li[j][c];
+            for (int j = c; j < n; ++j) C[c * ld + j] = Li[j][c];
         }
     } else if (w0 && lane < n) {
         const int j = lane;
         const double sjj = Sget(j, j);
         if (!(sjj > 0.0)) bad = true;
         const double nj = sqrt(sjj > 0.0 ? sjj : 1.0);
-        C[j * MAXO + j] = 1.0 / nj;
-        Cs[j * MAXO + j] = 1.0 / nj;
+        C[j * ld + j] = 1.0 / nj;
+        Cs[j * ld + j] = 1.0 / nj;
         for (int l = 0; l < j; ++l) {
             const double sll = Sget(l, l);
             const double nl = sqrt(sll > 0.0 ? sll : 1.0);
-            Cs[l * MAXO + j] = -(Sget(j, l) / (nj * nl)) / nl;
+            Cs[l * ld + j] = -(Sget(j, l) / (nj * nl)) / nl;
         }
     }
+    return bad;
+}
+
+// S from the tile partials (fixed order), then C and C* (ortho_coefficients).
+// Instances that fold the overlap (FOLD_S) are left to the orthonormalisation.
+__global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restrict__ descs,
+                                                         const int *__restrict__ list)
+{
+    const GroupRef gr = resolve_group(list);
+    const InstDesc &d = descs[gr.inst];
+    if (d.fold & FOLD_S) return;   // uniform per instance
+    const int n = d.n_orb, np = npair_of(n);
+    __shared__ double S[MAXO * (MAXO + 1) / 2];
+    if (!reduce_columns(d.s_part, d.ntile, np, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, S)) return;
+    const int lane = threadIdx.x;
+    bool bad = false;
+    if (threadIdx.x < 64)
+        for (int q = lane; q < np; q += 64) {
+            S[q] *= d.h3;
+            d.scal[SC_S + q] = S[q];
+            if (!isfinite(S[q])) bad = true;
+        }
+    __syncthreads();
+    // entries outside the n x n block stay zero from creation
+    if (ortho_coefficients<MAXO>(S, n, d.ortho, d.C, d.C + MAXO * MAXO, MAXO)) bad = true;
     bad = __any(bad);
     if (bad && lane == 0) d.scal[SC_ERR] = 1.0;   // lane 0 of the first wave: bad only ever set there
 }
 
 // psi_hat = psi C (psi* = psi C* in W mode), rho = sum_j occ_j psi_hat_j^2 and
-// the multipole partials q, p_a, Q_ab of rho.
+// the multipole partials q, p_a, Q_ab of rho.  An instance that folds the overlap
+// (FOLD_S, at most five orbitals) has no finalize kernel before this one: every
+// workgroup sums S from the tile partials in that kernel's order (fold_columns)
+// and forms C and C* itself, and the workgroup of tile 0 also stores what the
+// finalize kernel stores (S, C, C*, the error flag) for the kernels after this one.
 template <typename T, int NO, bool W>
 __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restrict__ descs,
                                                        const int2 *__restrict__ tiles)
@@ -224,6 +242,41 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
     const int n = orbitals<NO>(d);
+    constexpr bool FOLDS = NO <= 5;
+    constexpr int NF = FOLDS ? NO : 1;
+    __shared__ double fC[2][NF * NF];   // this workgroup's C and C* ([l * NO + j]) when folded
+    const bool fold = FOLDS && (d.fold & FOLD_S);   // uniform per workgroup
+    if constexpr (FOLDS) {
+        if (fold) {
+            __shared__ double fS[NF * (NF + 1) / 2];
+            const int np = npair_of(n), t = threadIdx.x;
+            if (t < 2 * NF * NF) fC[t / (NF * NF)][t % (NF * NF)] = 0.0;
+            fold_columns(d.s_part, d.ntile, np, fS);
+            bool bad = false;
+            if (t < np) {
+                fS[t] *= d.h3;
+                if (!isfinite(fS[t])) bad = true;
+            }
+            __syncthreads();
+            if (ortho_coefficients<NF>(fS, n, d.ortho, fC[0], fC[1], NF)) bad = true;
+            __syncthreads();
+            if (tr.tile == 0) {
+                if (t < np) d.scal[SC_S + t] = fS[t];
+                if (t < NF * NF) {
+                    const int l = t / NF, j = t % NF;
+                    if (l <= j && j < n) {
+                        if (d.ortho == 0) d.C[l * MAXO + j] = fC[0][t];
+                        else {
+                            if (l == j) d.C[j * MAXO + j] = fC[0][t];
+                            d.C[MAXO * MAXO + l * MAXO + j] = fC[1][t];
+                        }
+                    }
+                }
+                bad = __any(bad);
+                if (bad && t == 0) d.scal[SC_ERR] = 1.0;   // set in the first wave only
+            }
+        }
+    }
     const int s = tr.tile * BS + threadIdx.x;
     double m[NMOM];
 #pragma unroll
@@ -248,8 +301,14 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
                 occ[j] = (j < n) ? d.occ[j] : 0.0;
 #pragma unroll
                 for (int l = 0; l < NO; ++l) {
-                    c[l][j] = (l <= j && j < n) ? d.C[l * MAXO + j] : 0.0;
-                    cs[l][j] = (W && l <= j && j < n) ? d.C[MAXO * MAXO + l * MAXO + j] : 0.0;
+                    const bool use = l <= j && j < n;
+                    if (fold) {
+                        c[l][j] = use ? fC[0][l * NF + j] : 0.0;
+                        cs[l][j] = (W && use) ? fC[1][l * NF + j] : 0.0;
+                    } else {
+                        c[l][j] = use ? d.C[l * MAXO + j] : 0.0;
+                        cs[l][j] = (W && use) ? d.C[MAXO * MAXO + l * MAXO + j] : 0.0;
+                    }
                 }
             }
         }
@@ -301,11 +360,13 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 
 // ---------------------------------------------------------------- Hartree
 
+// Instances that fold the multipoles (FOLD_M) are left to the ghost-face kernel.
 __global__ __launch_bounds__(BS) void k_multipole_finalize(const InstDesc *__restrict__ descs,
                                                            const int *__restrict__ list)
 {
     const GroupRef gr = resolve_group(list);
     const InstDesc &d = descs[gr.inst];
+    if (d.fold & FOLD_M) return;   // uniform per instance
     __shared__ double m[NMOM];
     if (!reduce_columns(d.m_part, d.ntile, NMOM, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, m)) return;
     if ((int)threadIdx.x < NMOM) d.scal[SC_MOM + threadIdx.x] = m[threadIdx.x] * d.h3;
@@ -322,11 +383,26 @@ __device__ __forceinline__ double multipole_potential(const double *m, double x,
     return m[0] / r + (m[1] * x + m[2] * y + m[3] * z) / r3 + 0.5 * quad / r5;
 }
 
+// The far field on the six ghost faces.  An instance that folds the multipoles
+// (FOLD_M) has no finalize kernel before this one: every workgroup sums them from
+// the tile partials in that kernel's order (fold_columns), and the workgroup of
+// tile 0 also stores them.
 __global__ __launch_bounds__(BS) void k_ghost(const InstDesc *__restrict__ descs,
                                               const int2 *__restrict__ tiles)
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
+    __shared__ double fm[NMOM];
+    const double *mom = d.scal + SC_MOM;
+    if (d.fold & FOLD_M) {   // uniform per workgroup
+        fold_columns(d.m_part, d.ntile, NMOM, fm);
+        if ((int)threadIdx.x < NMOM) {
+            fm[threadIdx.x] *= d.h3;
+            if (tr.tile == 0) d.scal[SC_MOM + threadIdx.x] = fm[threadIdx.x];
+        }
+        __syncthreads();
+        mom = fm;
+    }
     const int nx = d.nx, ny = d.ny, nz = d.nz;
     int g = tr.tile * BS + threadIdx.x;
     const int fx = ny * nz, fy = nx * nz, fz = nx * ny;
@@ -349,7 +425,7 @@ __global__ __launch_bounds__(BS) void k_ghost(const InstDesc *__restrict__ descs
         j = r / nx;
         k = side ? nz : -1;
     }
-    const double v = multipole_potential(d.scal + SC_MOM, node_coord(i, nx, d.h), node_coord(j, ny, d.h),
+    const double v = multipole_potential(mom, node_coord(i, nx, d.h), node_coord(j, ny, d.h),
                                          node_coord(k, nz, d.h));
     d.vh[((size_t)(k + 1) * (ny + 2) + (j + 1)) * (nx + 2) + (i + 1)] = v;
 }
@@ -929,6 +1005,7 @@ int launch_overlap_psi(const Plan &pl, hipStream_t st, bool skip_brick)
 
 int launch_overlap_finalize(const Plan &pl, hipStream_t st)
 {
+    if (pl.fold_s) return 0;   // every instance's orthonormalisation sums S itself
     k_overlap_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }
@@ -944,6 +1021,7 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st)
 
 int launch_multipole_finalize(const Plan &pl, hipStream_t st)
 {
+    if (pl.fold_m) return 0;   // every instance's ghost-face kernel sums the multipoles itself
     k_multipole_finalize<<<grid_group(pl), BS, 0, st>>>(pl.d_desc, pl.tt.inst);
     LAUNCH_CHECK();
 }

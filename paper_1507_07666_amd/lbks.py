@@ -39,7 +39,7 @@ class lbks_params(Structure):
                 ("softening", c_double), ("init", c_int32), ("init_sigma", c_double),
                 ("init_noise", c_double), ("seed", c_uint64), ("rho_floor", c_double),
                 ("scheme", c_int32), ("stop_checks", c_int32), ("deps_tol", c_double),
-                ("hermite", c_int32), ("reserved", c_int32 * 3)]
+                ("hermite", c_int32), ("fold", c_int32), ("reserved", c_int32 * 2)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -92,6 +92,7 @@ SIGNATURES = {
     "lbks_copy_kernel": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lbks_set_variant": (c_int32, [c_void_p, c_int32]),
     "lbks_get_variant": (c_int32, [c_void_p]),
+    "lbks_get_fold": (c_int32, [c_void_p]),
     "lbks_autotune": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), POINTER(c_double)]),
     "lbks_batch_create": (c_int32, [POINTER(lbks_device), POINTER(c_void_p)]),
     "lbks_batch_attach": (c_int32, [c_void_p, c_void_p]),
@@ -380,6 +381,11 @@ class Solver:
 
     def variant(self) -> int:
         return load().lbks_get_variant(self.ctx)
+
+    def fold(self) -> int:
+        """Bit 0: the overlap totals are summed by the orthonormalisation; bit 1:
+        the multipole totals by the ghost-face kernel."""
+        return load().lbks_get_fold(self.ctx)
 
     def autotune(self, reps: int = 5, force: bool = False):
         """Pick the fastest update-kernel variant on the current state; returns

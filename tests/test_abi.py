@@ -86,6 +86,9 @@ def test_parameter_validation_host_side(L):
     p = lbks.params(16, 0.3, 1, 2)
     p.reserved[0] = 1
     assert L.lbks_estimate_bytes(ctypes.byref(p)) == 0
+    for fold, ok_ in ((0, True), (-1, True), (1, False), (2, False)):
+        p = lbks.params(16, 0.3, 1, 2, fold=fold)
+        assert (L.lbks_estimate_bytes(ctypes.byref(p)) > 0) == ok_, fold
     fp32 = lbks.params(32, 0.3, 1, 2, precision=lbks.LBKS_FP32_BULK)
     assert L.lbks_estimate_bytes(ctypes.byref(fp32)) < est
     coll = lbks.params(32, 0.3, 1, 2, scheme=lbks.LBKS_SCHEME_COLLAPSED)
