@@ -112,6 +112,13 @@ def test_create_rejects_invalid_params_before_touching_a_device(L):
         lbks.lbks_create(p)
     assert ei.value.code == lbks.LBKS_E_INVAL
     assert "7/18" in str(ei.value)
+    p = lbks.params(16, 0.3, 1, 2, fold=3)
+    with pytest.raises(lbks.LbksError) as ei:
+        lbks.lbks_create(p)
+    assert ei.value.code == lbks.LBKS_E_INVAL and "fold" in str(ei.value)
+    # the queries of a context refuse a NULL one without a device
+    assert lbks.load().lbks_get_fold(None) == lbks.LBKS_E_INVAL
+    assert lbks.load().lbks_get_variant(None) == lbks.LBKS_E_INVAL
 
 
 def test_bench_refuses_several_gpus():

@@ -125,6 +125,9 @@ assert L.lbks_batch_create(None, ctypes.byref(b)) != 0 and not b.value
 assert L.lbks_energy(None, None) == lbks.LBKS_E_INVAL
 assert L.lbks_cd_step(None, 1) == lbks.LBKS_E_INVAL
 assert L.lbks_batch_size(None) == 0
+assert L.lbks_get_fold(None) == lbks.LBKS_E_INVAL
+q = lbks.params(24, 0.3, 2, 4, fold=-2)
+assert L.lbks_estimate_bytes(ctypes.byref(q)) == 0
 L.lbks_destroy(None)
 L.lbks_batch_destroy(None)
 print("SANITIZED RUN OK")
