@@ -398,7 +398,8 @@ int lbks_kernel_time(lbks_ctx *ctx, int32_t kernel, double *total_ms, int64_t *l
  * z (8, 12, 16, 24 nodes) and bit 2 as its workgroup order; the collapsed
  * node-per-lane update ignores bit 3.
  * Defaults before autotuning: 13 for the population update of at most five
- * orbitals, 0 (FP64) or 1 (FP32) for the brick update, otherwise 4 (FP64) or 3
+ * orbitals on grids of more than 65536 nodes (0 (FP64) or 1 (FP32) on smaller
+ * ones), 0 (FP64) or 1 (FP32) for the brick update, otherwise 4 (FP64) or 3
  * (FP32).  lbks_set_variant: LBKS_E_INVAL outside 0..15. */
 int lbks_set_variant(lbks_ctx *ctx, int32_t variant);
 int lbks_get_variant(const lbks_ctx *ctx);
