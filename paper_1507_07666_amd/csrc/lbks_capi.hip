@@ -328,16 +328,17 @@ int plan_orthonormalise(const Plan &pl, hipStream_t st)
     return 0;
 }
 
-// Everything of one lattice step before the lattice Boltzmann update.
-int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
+// V of the current density: the multipole boundary, `sweeps` red/black SOR
+// sweeps warm-started from the last V_H, the potential.  When every instance
+// folds its multipoles the first red half-sweep also writes the ghost faces.
+int plan_hartree_potential(const Plan &pl, int hartree, int sweeps, hipStream_t st)
 {
-    PCHK(plan_orthonormalise(pl, st));
-    if (pl.gga) PCHK(launch_gga(pl, st));
     if (hartree) {
-        PCHK(launch_multipole_finalize(pl, st));
-        PCHK(launch_ghost(pl, st));
+        PCHK(launch_multipole_finalize(pl, st));   // launches nothing when every instance folds
+        const bool first = pl.fold_m && sweeps > 0;
+        if (!first) PCHK(launch_ghost(pl, st));
         for (int k = 0; k < sweeps; ++k) {
-            PCHK(launch_sor(pl, 0, st));
+            PCHK(k == 0 && first ? launch_sor_first(pl, st) : launch_sor(pl, 0, st));
             if (k + 1 < sweeps) PCHK(launch_sor(pl, 1, st));
         }
         // the last black half-sweep also evaluates the potential
@@ -345,6 +346,14 @@ int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
     }
     PCHK(launch_potential(pl, 0, st));
     return 0;
+}
+
+// Everything of one lattice step before the lattice Boltzmann update.
+int plan_pre_update(const Plan &pl, int hartree, int sweeps, hipStream_t st)
+{
+    PCHK(plan_orthonormalise(pl, st));
+    if (pl.gga) PCHK(launch_gga(pl, st));
+    return plan_hartree_potential(pl, hartree, sweeps, st);
 }
 
 int plan_update(const Plan &pl, int scheme, int parity, hipStream_t st)
@@ -1001,21 +1010,7 @@ double2 *cd_level(lbks_ctx *c, int k) { return c->cd_buf + (size_t)k * c->p.n_or
 // V of the density in place: multipole boundary, K_P red/black sweeps, potential.
 int cd_potential(lbks_ctx *c)
 {
-    const Plan &pl = c->plan;
-    if (c->p.hartree) {
-        KCHK(c, launch_multipole_finalize(pl, c->stream));
-        KCHK(c, launch_ghost(pl, c->stream));
-        const int sw = c->p.poisson_sweeps;
-        for (int k = 0; k < sw; ++k) {
-            KCHK(c, launch_sor(pl, 0, c->stream));
-            if (k + 1 < sw) KCHK(c, launch_sor(pl, 1, c->stream));
-        }
-        if (sw > 0) {
-            KCHK(c, launch_sor_black_potential(pl, c->stream));
-            return 0;
-        }
-    }
-    KCHK(c, launch_potential(pl, 0, c->stream));
+    KCHK(c, plan_hartree_potential(c->plan, c->p.hartree, c->p.poisson_sweeps, c->stream));
     return 0;
 }
 

@@ -278,9 +278,26 @@ __device__ __forceinline__ void fold_columns(const double *__restrict__ part, in
     else fold_columns_l<16>(part, ntile, nq, grp, out);
 }
 
+// Coordinate of node i of n (the grid centred on the origin).  Here, in
+// multipole_potential and in sor_node no multiply is fused into an add: each
+// is inlined into several kernels, and the fusions the compiler finds depend on
+// the code around it, so a value two kernels must agree on bit for bit (a ghost
+// face written by one and recomputed by another) has to be computed the same way
+// everywhere.
 __device__ __forceinline__ double node_coord(int i, int n, double h)
 {
+#pragma clang fp contract(off)
     return ((double)i - 0.5 * (double)(n - 1)) * h;
+}
+
+// One successive over-relaxation update of V_H at a node from the sum of its six
+// neighbours: V <- (1 - w) V + w (nb + 4 pi h^2 rho) / 6.
+__device__ __forceinline__ double sor_node(double nb, double rho, double old, double h, double omega)
+{
+#pragma clang fp contract(off)
+    const double four_pi_h2 = 4.0 * 3.14159265358979323846 * h * h;
+    const double gs = (nb + four_pi_h2 * rho) / 6.0;
+    return (1.0 - omega) * old + omega * gs;
 }
 
 __device__ __forceinline__ int npair_of(int n) { return n * (n + 1) / 2; }

@@ -167,6 +167,7 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st);
 int launch_multipole_finalize(const Plan &pl, hipStream_t st);
 int launch_ghost(const Plan &pl, hipStream_t st);
 int launch_sor(const Plan &pl, int color, hipStream_t st);
+int launch_sor_first(const Plan &pl, hipStream_t st);   // red, with the ghost faces (every instance FOLD_M)
 int launch_sor_black_potential(const Plan &pl, hipStream_t st);   // last black half-sweep + V
 int launch_potential(const Plan &pl, int to_fp64, hipStream_t st);
 int launch_stream_collide(const Plan &pl, int parity, hipStream_t st);

@@ -375,12 +375,44 @@ __global__ __launch_bounds__(BS) void k_multipole_finalize(const InstDesc *__res
 // Far field of the multipoles: q/r + p.r/r^3 + (1/2) sum_ab Q_ab r_a r_b / r^5.
 __device__ __forceinline__ double multipole_potential(const double *m, double x, double y, double z)
 {
+#pragma clang fp contract(off)   // computed the same way in every kernel (see node_coord)
     const double r2 = x * x + y * y + z * z;
     const double r = sqrt(r2);
     const double r3 = r2 * r, r5 = r3 * r2;
     const double quad = m[4] * x * x + m[5] * y * y + m[6] * z * z
                       + 2.0 * (m[7] * x * y + m[8] * x * z + m[9] * y * z);
     return m[0] / r + (m[1] * x + m[2] * y + m[3] * z) / r3 + 0.5 * quad / r5;
+}
+
+// Ghost-face node g of 2 (ny nz + nx nz + nx ny): the two x faces (i = -1, nx),
+// then the y faces, then the z faces, each in row order of its other two indices.
+__device__ __forceinline__ int3 ghost_node(int g, int nx, int ny, int nz)
+{
+    const int fx = ny * nz, fy = nx * nz, fz = nx * ny;
+    if (g < 2 * fx) {
+        const int side = g / fx, r = g % fx;
+        return make_int3(side ? nx : -1, r % ny, r / ny);
+    }
+    if ((g -= 2 * fx) < 2 * fy) {
+        const int side = g / fy, r = g % fy;
+        return make_int3(r % nx, side ? ny : -1, r / nx);
+    }
+    g -= 2 * fy;
+    const int side = g / fz, r = g % fz;
+    return make_int3(r % nx, r / nx, side ? nz : -1);
+}
+
+// The multipoles (h^3 included) of an instance that folds them, summed by this
+// workgroup from the tile partials in the finalize kernel's order; the workgroup
+// of tile 0 also stores them.  Every thread of the workgroup calls this.
+__device__ __forceinline__ void fold_multipoles(const InstDesc &d, int tile, double *fm)
+{
+    fold_columns(d.m_part, d.ntile, NMOM, fm);
+    if ((int)threadIdx.x < NMOM) {
+        fm[threadIdx.x] *= d.h3;
+        if (tile == 0) d.scal[SC_MOM + threadIdx.x] = fm[threadIdx.x];
+    }
+    __syncthreads();
 }
 
 // The far field on the six ghost faces.  An instance that folds the multipoles
@@ -395,36 +427,14 @@ __global__ __launch_bounds__(BS) void k_ghost(const InstDesc *__restrict__ descs
     __shared__ double fm[NMOM];
     const double *mom = d.scal + SC_MOM;
     if (d.fold & FOLD_M) {   // uniform per workgroup
-        fold_columns(d.m_part, d.ntile, NMOM, fm);
-        if ((int)threadIdx.x < NMOM) {
-            fm[threadIdx.x] *= d.h3;
-            if (tr.tile == 0) d.scal[SC_MOM + threadIdx.x] = fm[threadIdx.x];
-        }
-        __syncthreads();
+        fold_multipoles(d, tr.tile, fm);
         mom = fm;
     }
     const int nx = d.nx, ny = d.ny, nz = d.nz;
-    int g = tr.tile * BS + threadIdx.x;
-    const int fx = ny * nz, fy = nx * nz, fz = nx * ny;
-    if (g >= 2 * (fx + fy + fz)) return;
-    int i, j, k;
-    if (g < 2 * fx) {
-        const int side = g / fx, r = g % fx;
-        j = r % ny;
-        k = r / ny;
-        i = side ? nx : -1;
-    } else if ((g -= 2 * fx) < 2 * fy) {
-        const int side = g / fy, r = g % fy;
-        i = r % nx;
-        k = r / nx;
-        j = side ? ny : -1;
-    } else {
-        g -= 2 * fy;
-        const int side = g / fz, r = g % fz;
-        i = r % nx;
-        j = r / nx;
-        k = side ? nz : -1;
-    }
+    const int g = tr.tile * BS + threadIdx.x;
+    if (g >= 2 * (ny * nz + nx * nz + nx * ny)) return;
+    const int3 q = ghost_node(g, nx, ny, nz);
+    const int i = q.x, j = q.y, k = q.z;
     const double v = multipole_potential(mom, node_coord(i, nx, d.h), node_coord(j, ny, d.h),
                                          node_coord(k, nz, d.h));
     d.vh[((size_t)(k + 1) * (ny + 2) + (j + 1)) * (nx + 2) + (i + 1)] = v;
@@ -449,10 +459,65 @@ __global__ __launch_bounds__(BS) void k_sor(const InstDesc *__restrict__ descs,
     const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(x + 1);
     auto *vh = gmem(d.vh);
     const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
-    const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
     const double rho = (double)gmem((const T *)d.rho)[((size_t)z * ny + y) * nx + x];
-    const double gs = (nb + four_pi_h2 * rho) / 6.0;
-    vh[idx] = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
+    vh[idx] = sor_node(nb, rho, vh[idx], d.h, d.omega_sor);
+}
+
+// The first red half-sweep of a lattice step when every instance of the launch
+// folds its multipoles (FOLD_M): it also does the ghost-face kernel's work, one
+// launch fewer.  Every workgroup sums the multipoles (fold_multipoles); the
+// workgroups write the six ghost faces between them (the values k_ghost writes,
+// for the sweeps after this one); a red node next to the boundary takes its ghost
+// neighbour from the same far-field expression instead of from memory, which this
+// launch is writing.  The sweep is k_sor's, addition for addition.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_sor_first(const InstDesc *__restrict__ descs,
+                                                  const int2 *__restrict__ tiles)
+{
+    const TileRef tr = resolve(tiles);
+    const InstDesc &d = descs[tr.inst];
+    const int nx = d.nx, ny = d.ny, nz = d.nz;
+    const double h = d.h;
+    const size_t P = (size_t)nx + 2, PP = P * (size_t)(ny + 2);
+    auto *vh = gmem(d.vh);
+    // the sweep's operands inside the grid first: they do not depend on the
+    // multipoles, so their loads are in flight while those are summed
+    const int hx = (nx + 1) >> 1;
+    const int t = tr.tile * BS + threadIdx.x;
+    const int xh = t % hx, yz = t / hx, y = yz % ny, z = yz / ny;
+    const int x = 2 * xh + ((y + z) & 1);   // red
+    const bool node = t < hx * ny * nz && x < nx;
+    const size_t idx = (size_t)(z + 1) * PP + (size_t)(y + 1) * P + (size_t)(x + 1);
+    const int nbx[6] = {x - 1, x + 1, x, x, x, x}, nby[6] = {y, y, y - 1, y + 1, y, y},
+              nbz[6] = {z, z, z, z, z - 1, z + 1};
+    const long long off[6] = {-1, 1, -(long long)P, (long long)P, -(long long)PP, (long long)PP};
+    double v[6], rho = 0.0, old = 0.0;
+    bool ghost[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        ghost[q] = nbx[q] < 0 || nbx[q] >= nx || nby[q] < 0 || nby[q] >= ny || nbz[q] < 0 || nbz[q] >= nz;
+        v[q] = node && !ghost[q] ? (double)vh[(size_t)((long long)idx + off[q])] : 0.0;
+    }
+    if (node) {
+        rho = (double)gmem((const T *)d.rho)[((size_t)z * ny + y) * nx + x];
+        old = vh[idx];
+    }
+    __shared__ double fm[NMOM];
+    fold_multipoles(d, tr.tile, fm);
+    const int nghost = 2 * (ny * nz + nx * nz + nx * ny);
+    for (int g = tr.tile * BS + (int)threadIdx.x; g < nghost; g += d.ntile_sor * BS) {
+        const int3 c = ghost_node(g, nx, ny, nz);
+        vh[(size_t)(c.z + 1) * PP + (size_t)(c.y + 1) * P + (size_t)(c.x + 1)] =
+            multipole_potential(fm, node_coord(c.x, nx, h), node_coord(c.y, ny, h), node_coord(c.z, nz, h));
+    }
+    if (!node) return;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        if (ghost[q])
+            v[q] = multipole_potential(fm, node_coord(nbx[q], nx, h), node_coord(nby[q], ny, h),
+                                       node_coord(nbz[q], nz, h));
+    const double nb = v[0] + v[1] + v[2] + v[3] + v[4] + v[5];
+    vh[idx] = sor_node(nb, rho, old, h, d.omega_sor);
 }
 
 // Residual partials: sum (lap_h V_H + 4 pi rho)^2 and sum (4 pi rho)^2.
@@ -614,10 +679,8 @@ __global__ __launch_bounds__(BS) void k_sor_black_potential(const InstDesc *__re
     double vb = 0.0, Vb = 0.0, Vr = 0.0;
     if (xb < nx) {
         const double nb = vh[idx - 1] + vh[idx + 1] + vh[idx - P] + vh[idx + P] + vh[idx - PP] + vh[idx + PP];
-        const double four_pi_h2 = 4.0 * 3.14159265358979323846 * d.h * d.h;
         const double rho = (double)gmem((const T *)d.rho)[((size_t)z * ny + y) * nx + xb];
-        const double gs = (nb + four_pi_h2 * rho) / 6.0;
-        vb = (1.0 - d.omega_sor) * vh[idx] + d.omega_sor * gs;
+        vb = sor_node(nb, rho, vh[idx], d.h, d.omega_sor);
         Vb = potential_with<T>(d, sb, xb, y, z, vb);
     }
     if (xr < nx) Vr = potential_at<T>(d, sr, xr, y, z);   // red V_H is not written here
@@ -1037,6 +1100,15 @@ int launch_sor(const Plan &pl, int color, hipStream_t st)
     return dispatch_tt(pl, [&](auto tg) {
         using TG = decltype(tg);
         k_sor<typename TG::T><<<grid_sor(pl), BS, 0, st>>>(pl.d_desc, pl.tt.sor, color);
+        LAUNCH_CHECK();
+    });
+}
+
+int launch_sor_first(const Plan &pl, hipStream_t st)
+{
+    return dispatch_tt(pl, [&](auto tg) {
+        using TG = decltype(tg);
+        k_sor_first<typename TG::T><<<grid_sor(pl), BS, 0, st>>>(pl.d_desc, pl.tt.sor);
         LAUNCH_CHECK();
     });
 }
