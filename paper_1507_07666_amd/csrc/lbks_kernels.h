@@ -48,9 +48,12 @@ __host__ __device__ constexpr int padded_cols(int nq) { return (nq + RCH - 1) / 
 // next: every workgroup of that kernel sums the tile partials itself, in the
 // finalize kernel's order of additions, so the results are the same bit for bit.
 // The overlap S goes to the orthonormalisation (up to five orbitals), the
-// multipoles to the ghost-face kernel, for instances of at most RG * FOLD_GROUP
-// tiles (measured on MI355X: 48.5 -> 39.2 us per step at 32^3; with 432 or 1024
-// tiles the multipole fold alone no longer pays).  InstDesc::fold holds the bits.
+// multipoles to the ghost-face kernel or the step's first red sweep, for
+// instances of at most RG * FOLD_GROUP tiles (measured on MI355X: 48.5 -> 39.2 us
+// per step at 32^3; with 432 or 1024 tiles the multipole fold alone no longer
+// pays).  InstDesc::fold holds the bits an instance allows; a launch folds when
+// every instance in it allows (Plan::fold_s, fold_m), so a mixed batch takes the
+// finalize kernels for all its members, which gives the same bits.
 constexpr int FOLD_S = 1, FOLD_M = 2;
 constexpr int FOLD_GROUP = 16;   // tiles per first-level group, at most
 inline int fold_bits(int ntile, int n_orb, bool enabled)
@@ -81,7 +84,7 @@ struct InstDesc {
     int nnuc;                  // nuclei set by lbks_set_nuclei (0 after lbks_set_potential)
     unsigned active;           // orbitals that take the omega = 1 field update (bit j); the others keep
                                // their fields (the sequential Gram-Schmidt order); all ones otherwise
-    int fold;                  // FOLD_S / FOLD_M: the overlap / multipole totals are summed by their consumer
+    int fold;                  // FOLD_S / FOLD_M: the overlap / multipole totals may be summed by their consumer
     double h, h3, omega, dt, D, omega_sor, rho_floor, e_nn;
     double occ[MAXO];
     double xi[Q], chi[Q];

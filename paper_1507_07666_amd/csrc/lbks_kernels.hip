@@ -204,13 +204,12 @@ __device__ bool ortho_coefficients(const double *S, int n, int ortho, double *C,
 }
 
 // S from the tile partials (fixed order), then C and C* (ortho_coefficients).
-// Instances that fold the overlap (FOLD_S) are left to the orthonormalisation.
+// Not launched when every instance of the plan folds the overlap.
 __global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restrict__ descs,
                                                          const int *__restrict__ list)
 {
     const GroupRef gr = resolve_group(list);
     const InstDesc &d = descs[gr.inst];
-    if (d.fold & FOLD_S) return;   // uniform per instance
     const int n = d.n_orb, np = npair_of(n);
     __shared__ double S[MAXO * (MAXO + 1) / 2];
     if (!reduce_columns(d.s_part, d.ntile, np, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, S)) return;
@@ -230,24 +229,25 @@ __global__ __launch_bounds__(BS) void k_overlap_finalize(const InstDesc *__restr
 }
 
 // psi_hat = psi C (psi* = psi C* in W mode), rho = sum_j occ_j psi_hat_j^2 and
-// the multipole partials q, p_a, Q_ab of rho.  An instance that folds the overlap
-// (FOLD_S, at most five orbitals) has no finalize kernel before this one: every
-// workgroup sums S from the tile partials in that kernel's order (fold_columns)
-// and forms C and C* itself, and the workgroup of tile 0 also stores what the
-// finalize kernel stores (S, C, C*, the error flag) for the kernels after this one.
-template <typename T, int NO, bool W>
+// the multipole partials q, p_a, Q_ab of rho.  FOLD (every instance of the launch
+// folds the overlap, at most five orbitals): there is no finalize kernel before
+// this one; every workgroup sums S from the tile partials in that kernel's order
+// (fold_columns) and forms C and C* itself, and the workgroup of tile 0 also
+// stores what the finalize kernel stores (S, C, C*, the error flag) for the
+// kernels after this one.  Without FOLD the kernel reads C from memory, with no
+// trace of the fold in its code.
+template <typename T, int NO, bool W, bool FOLD>
 __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restrict__ descs,
                                                        const int2 *__restrict__ tiles)
 {
+    static_assert(!FOLD || NO <= 5, "the fold serves buckets of at most five orbitals");
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
     const int n = orbitals<NO>(d);
-    constexpr bool FOLDS = NO <= 5;
-    constexpr int NF = FOLDS ? NO : 1;
-    __shared__ double fC[2][NF * NF];   // this workgroup's C and C* ([l * NO + j]) when folded
-    const bool fold = FOLDS && (d.fold & FOLD_S);   // uniform per workgroup
-    if constexpr (FOLDS) {
-        if (fold) {
+    constexpr int NF = FOLD ? NO : 1;
+    [[maybe_unused]] __shared__ double fC[2][NF * NF];   // this workgroup's C and C* ([l * NO + j]) when folded
+    if constexpr (FOLD) {
+        {
             __shared__ double fS[NF * (NF + 1) / 2];
             const int np = npair_of(n), t = threadIdx.x;
             if (t < 2 * NF * NF) fC[t / (NF * NF)][t % (NF * NF)] = 0.0;
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 #pragma unroll
                 for (int l = 0; l < NO; ++l) {
                     const bool use = l <= j && j < n;
-                    if (fold) {
+                    if constexpr (FOLD) {
                         c[l][j] = use ? fC[0][l * NF + j] : 0.0;
                         cs[l][j] = (W && use) ? fC[1][l * NF + j] : 0.0;
                     } else {
@@ -360,13 +360,12 @@ __global__ __launch_bounds__(BS) void k_orthonormalise(const InstDesc *__restric
 
 // ---------------------------------------------------------------- Hartree
 
-// Instances that fold the multipoles (FOLD_M) are left to the ghost-face kernel.
+// Not launched when every instance of the plan folds the multipoles.
 __global__ __launch_bounds__(BS) void k_multipole_finalize(const InstDesc *__restrict__ descs,
                                                            const int *__restrict__ list)
 {
     const GroupRef gr = resolve_group(list);
     const InstDesc &d = descs[gr.inst];
-    if (d.fold & FOLD_M) return;   // uniform per instance
     __shared__ double m[NMOM];
     if (!reduce_columns(d.m_part, d.ntile, NMOM, d.g_part, (unsigned *)(d.scal + SC_CNT), gr.g, m)) return;
     if ((int)threadIdx.x < NMOM) d.scal[SC_MOM + threadIdx.x] = m[threadIdx.x] * d.h3;
@@ -415,18 +414,18 @@ __device__ __forceinline__ void fold_multipoles(const InstDesc &d, int tile, dou
     __syncthreads();
 }
 
-// The far field on the six ghost faces.  An instance that folds the multipoles
-// (FOLD_M) has no finalize kernel before this one: every workgroup sums them from
-// the tile partials in that kernel's order (fold_columns), and the workgroup of
-// tile 0 also stores them.
+// The far field on the six ghost faces.  fold (every instance of the launch folds
+// the multipoles): there is no finalize kernel before this one; every workgroup
+// sums them from the tile partials in that kernel's order (fold_columns), and the
+// workgroup of tile 0 also stores them.
 __global__ __launch_bounds__(BS) void k_ghost(const InstDesc *__restrict__ descs,
-                                              const int2 *__restrict__ tiles)
+                                              const int2 *__restrict__ tiles, int fold)
 {
     const TileRef tr = resolve(tiles);
     const InstDesc &d = descs[tr.inst];
     __shared__ double fm[NMOM];
     const double *mom = d.scal + SC_MOM;
-    if (d.fold & FOLD_M) {   // uniform per workgroup
+    if (fold) {   // uniform
         fold_multipoles(d, tr.tile, fm);
         mom = fm;
     }
@@ -1077,7 +1076,14 @@ int launch_orthonormalise(const Plan &pl, hipStream_t st)
 {
     return dispatch_tnw(pl, [&](auto tg) {
         using TG = decltype(tg);
-        k_orthonormalise<typename TG::T, TG::NO, TG::W><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
+        if constexpr (TG::NO <= 5) {
+            if (pl.fold_s) {
+                k_orthonormalise<typename TG::T, TG::NO, TG::W, true><<<grid_site(pl), BS, 0, st>>>(pl.d_desc,
+                                                                                                    pl.tt.site);
+                LAUNCH_CHECK();
+            }
+        }
+        k_orthonormalise<typename TG::T, TG::NO, TG::W, false><<<grid_site(pl), BS, 0, st>>>(pl.d_desc, pl.tt.site);
         LAUNCH_CHECK();
     });
 }
@@ -1091,7 +1097,7 @@ int launch_multipole_finalize(const Plan &pl, hipStream_t st)
 
 int launch_ghost(const Plan &pl, hipStream_t st)
 {
-    k_ghost<<<grid_ghost(pl), BS, 0, st>>>(pl.d_desc, pl.tt.ghost);
+    k_ghost<<<grid_ghost(pl), BS, 0, st>>>(pl.d_desc, pl.tt.ghost, pl.fold_m ? 1 : 0);
     LAUNCH_CHECK();
 }
 

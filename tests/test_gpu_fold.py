@@ -91,8 +91,9 @@ def test_fold_equals_separate_reductions(L, name, make, kw, bits):
 
 
 def test_fold_in_a_mixed_batch(L):
-    """Folded and unfolded members in one group: the separate kernels run and
-    skip the members that fold; every member equals its run alone."""
+    """Members that fold alone and members that do not, in one group: the launch
+    folds only when every member does, so here the separate kernels serve them
+    all, and every member still equals its run alone bit for bit."""
     members = [
         (I.ne_atom().scaled(20, h=0.3), dict(fold=0)),
         (I.ne_atom().scaled(18, h=0.3), dict(fold=-1)),
