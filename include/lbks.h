@@ -117,9 +117,11 @@ typedef struct lbks_params {
     int32_t fold;            /* 0 (default): on grids of at most 65536 nodes (256 tiles of 256) the
                                 overlap totals (at most five orbitals) and the multipole totals are
                                 summed by every workgroup of the kernel that uses them, in the order
-                                of the separate reduction kernel: two launches fewer per lattice
-                                step, the same results bit for bit; -1: always by the separate
-                                kernels */
+                                of the separate reduction kernel, and the first red Poisson
+                                half-sweep of a step also writes the ghost faces: three launches
+                                fewer per lattice step, the same results bit for bit.  A batch
+                                launch folds when all its members allow it.  -1: always the
+                                separate kernels */
     int32_t reserved[2];     /* must be zero */
 } lbks_params;
 
