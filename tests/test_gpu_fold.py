@@ -133,3 +133,25 @@ def test_fold_in_concurrent_dynamics(L):
     (b0, psi0, E0, F0), (b1, psi1, E1, F1) = res
     assert b0 == FOLD_S | FOLD_M and b1 == 0
     assert same(psi0, psi1) and same(E0, E1) and same(F0, F1)
+
+
+def test_small_grid_defaults(L):
+    """Grids of at most 256 tiles start from the node-per-lane population update
+    (0 in FP64, 1 in FP32) and fold; larger ones start from the rolled wide form
+    (13) and do not; the brick update keeps its own defaults."""
+    cases = [
+        (I.he_atom(), {}, 0, FOLD_S | FOLD_M),                                  # 128 tiles
+        (I.he_atom(), dict(precision=1), 1, FOLD_S | FOLD_M),
+        (he_slab(16), {}, 0, FOLD_S | FOLD_M),                                  # 256 tiles
+        (he_slab(17), {}, 13, 0),                                               # 272 tiles
+        (he_slab(17), dict(precision=1), 13, 0),
+        (I.he_atom(), dict(fold=-1), 0, 0),
+        (I.he_atom(), dict(scheme=1), 0, FOLD_S | FOLD_M),                      # the brick update
+        (he_slab(17), dict(scheme=1, precision=1), 1, 0),
+        (I.atom(15, 20, h=0.35, softening=0.3, seed=8), {}, 4, FOLD_M),         # 8 orbitals
+    ]
+    for system, kw, variant, bits in cases:
+        s = L.Solver.for_system(system, **kw)
+        got = (s.variant(), s.fold())
+        s.close()
+        assert got == (variant, bits), (system.dims, kw, got)
